@@ -1,0 +1,218 @@
+/*
+ * fpssft.h — C ABI of the MI355X (gfx950) FPS-SFT hot path.
+ *
+ * FPS-SFT (Wang, Patel, Petropulu, arXiv 1711.11407) recovers the K on-grid
+ * sinusoids (a, w) of a D-dimensional cube x from samples taken along
+ * discrete lines (Sec. 2, problem statement after Eq. sigModel2). Every
+ * iteration gathers D+1 lines of length L = LCM(N_0..N_{D-1}) with one random
+ * slope alpha and offsets tau, tau + e_0, ..., tau + e_{D-1} (Eq. sample_slice;
+ * Multi-dimensional extension), takes their 1/L-normalised L-point DFTs
+ * (Eq. hs), subtracts the projections of the sinusoids recovered so far
+ * (construction-subtraction, Sec. 2.2), tests each bin for 1-sparsity and
+ * decodes frequency and amplitude from the phase differences between the
+ * shifted lines (Eq. decoding).
+ *
+ * Conventions shared by every entry point
+ *  - Cube layout: complex64 (interleaved float re, im), row-major, the last
+ *    dimension contiguous: flat(n) = sum_k n_k * prod_{j>k} N_j.
+ *  - Device pointers are HIP device addresses on the device that was
+ *    current when the plan was created; they stay owned by the caller.
+ *  - `stream` is a hipStream_t (NULL = the default stream). Device work is
+ *    stream-ordered and asynchronous; the host never waits unless stated.
+ *  - Nothing throws. Argument errors are returned synchronously and no
+ *    device work is enqueued. The algorithm's outcome (OK, INCOMPLETE,
+ *    CAPACITY) is written to device memory (fpssft_out.info).
+ *  - A plan owns device workspace: at most one call per plan may be in
+ *    flight at a time (calls on one stream are naturally serialised).
+ *  - The input cube is never modified.
+ */
+#ifndef FPSSFT_H
+#define FPSSFT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FPSSFT_MAX_D 4
+#define FPSSFT_ABI_VERSION 1
+
+/* Return codes (negative) and device-side outcomes (non-negative). */
+typedef enum {
+  FPSSFT_OK = 0,              /* device outcome: an empty residual was seen  */
+  FPSSFT_INCOMPLETE = 1,      /* device outcome: T_max reached, residual != 0 */
+  FPSSFT_CAPACITY = 2,        /* device outcome: max_k records, more found    */
+  FPSSFT_ERR_INVALID_ARG = -1,
+  FPSSFT_ERR_UNSUPPORTED = -2, /* valid, but beyond this build (LDS, 32-bit) */
+  FPSSFT_ERR_HIP = -3,         /* a HIP runtime call failed                   */
+  FPSSFT_ERR_NOMEM = -4,
+  FPSSFT_ERR_NO_DEVICE = -5
+} fpssft_status;
+
+/* One cube's problem description (host struct, copied by the plan).
+ *  ndim, dims   D in [1, FPSSFT_MAX_D] and N_k >= 1 (Sec. 2: x is defined on
+ *               [N_0] x ... x [N_{D-1}]). L = LCM(N_k) (Lemma 1).
+ *  max_iters    T_max; 0 selects floor(N / ((D+1) L)) but at least 1, the
+ *               paper's budget of about 100% of the samples (Sec. 3).
+ *  max_k        capacity of the record list (>= 1).
+ *  seed         seed of the SplitMix64 line schedule (below).
+ *  zero_thresh  theta0: a bin is nonzero iff |r| > theta0 (Sec. 2.2: a
+ *               nonzero bin is 1-sparse with high probability).
+ *  mag_rel_tol  rho: 1-sparse needs | |r_i(m)| - |r_0(m)| | <= rho |r_0(m)|
+ *               for every shifted line i (the magnitude test of Sec. 2.1).
+ *  grid_tol     gamma: the decoded u_k = N_k phi / (2 pi) must be within
+ *               gamma of an integer; gamma < 0 disables the check.
+ *  schedule     optional host array int32 [max_iters][2][ndim]: per
+ *               iteration the slope alpha then the offset tau, entries in
+ *               [0, N_k). NULL: drawn from `seed` (fpssft_schedule_generate).
+ *               When given, max_iters must be > 0; slopes outside Lemma 2's
+ *               set are accepted (e.g. axis-only schedules). */
+typedef struct {
+  int32_t ndim;
+  int32_t dims[FPSSFT_MAX_D];
+  int32_t max_iters;
+  int32_t max_k;
+  uint64_t seed;
+  float zero_thresh;
+  float mag_rel_tol;
+  float grid_tol;
+  const int32_t* schedule;
+} fpssft_desc;
+
+/* Per-cube outputs: all DEVICE pointers, caller-owned.
+ *  freqs     int32 [max_k][ndim]  recovered frequency indices m_k in [0, N_k)
+ *  amps      complex64 [max_k]    recovered amplitudes a (Eq. decoding)
+ *  rec_iter  int32 [max_k]        iteration that found each record
+ *  rec_bin   int32 [max_k]        its bin m in that iteration's lines
+ *  info      int32 [4]            k, iterations executed, outcome, reserved
+ * Records are in canonical order: iteration ascending, bin ascending. A
+ * frequency detected again in a later iteration is a further record (the
+ * recovered set is a list; its construction sums all records). Entries past
+ * info[0] are left unchanged. */
+typedef struct {
+  int32_t* freqs;
+  void* amps;
+  int32_t* rec_iter;
+  int32_t* rec_bin;
+  int32_t* info;
+} fpssft_out;
+
+/* Launch-shape choices of the autotuner (0 = library default).
+ *  block_threads  threads per work-group of the solve kernels (64..1024,
+ *                 multiple of 64)
+ *  max_radix      largest FFT radix used for power-of-two factors (2, 4, 8)
+ *  chunk_iters    iterations the plain path gathers and transforms ahead
+ *                 in parallel before its sequential decode (>= 0)
+ *  lines_wg       lines per work-group of the line gather + FFT kernel */
+typedef struct {
+  int32_t block_threads;
+  int32_t max_radix;
+  int32_t chunk_iters;
+  int32_t lines_wg;
+} fpssft_tuning;
+
+typedef struct fpssft_plan_st* fpssft_plan_t;
+
+/* ---- host-only calls (no device needed) ------------------------------- */
+
+/* Text for a status code. Static storage; never NULL. */
+const char* fpssft_strerror(int32_t status);
+
+/* FPSSFT_ABI_VERSION of the loaded library. */
+int32_t fpssft_abi_version(void);
+
+/* Check a description. On success writes L (Lemma 1) and the effective
+ * T_max to the optional outputs. INVALID_ARG for out-of-range fields;
+ * UNSUPPORTED when N_k * L >= 2^31 or N >= 2^40 (index arithmetic is exact
+ * 32-bit per dimension) or L > 65536. */
+fpssft_status fpssft_validate(const fpssft_desc* desc, int32_t* line_length,
+                              int32_t* max_iters);
+
+/* The line schedule that `desc` (with schedule == NULL) produces: host
+ * array int32 [T][2][ndim], iterations 0..T-1 (Sec. 2.2: a random slope in
+ * Lemma 2's set and a random offset each iteration). One SplitMix64 stream
+ * (Steele, Lea, Flood 2014) per cube, output i = mix(seed + (i+1) * 0x9E37...).
+ * A draw on [0, n) is floor(z * n / 2^64). Per iteration: draw alpha_0..
+ * alpha_{D-1}, redraw all D until gcd(c_0 alpha_0, ..., c_{D-1} alpha_{D-1})
+ * = 1 (c_k = L / N_k; Lemma 2's set in 2-D), then draw tau_0..tau_{D-1}. */
+fpssft_status fpssft_schedule_generate(const fpssft_desc* desc, int32_t T,
+                                       int32_t* alpha_tau);
+
+/* ---- plans ------------------------------------------------------------- */
+
+/* Build a plan for `batch` cubes on the current HIP device: validates every
+ * description, draws or copies the schedules, builds twiddle tables
+ * W_L^k = exp(-j 2 pi k / L) (fp64 on the host, rounded to fp32) and FFT
+ * factorisations, and uploads them. `tuning` may be NULL. */
+fpssft_status fpssft_plan_create(const fpssft_desc* descs, int32_t batch,
+                                 const fpssft_tuning* tuning, fpssft_plan_t* plan);
+
+/* Release the plan and its device memory (waits for the device). */
+fpssft_status fpssft_plan_destroy(fpssft_plan_t plan);
+
+/* Host copy of cube `cube`'s schedule, int32 [T_max][2][ndim]. */
+fpssft_status fpssft_plan_get_schedule(fpssft_plan_t plan, int32_t cube,
+                                       int32_t* alpha_tau);
+
+/* L, T_max and the element offset of cube `cube`'s block in the packed
+ * spectra buffer of fpssft_lines_fft_all (any output may be NULL). */
+fpssft_status fpssft_plan_cube_info(fpssft_plan_t plan, int32_t cube,
+                                    int32_t* line_length, int32_t* max_iters,
+                                    int64_t* spectra_offset);
+
+/* Total complex64 elements of the packed spectra buffer: sum over cubes of
+ * T_max * (D+1) * L. */
+int64_t fpssft_plan_spectra_elems(fpssft_plan_t plan);
+
+/* ---- the hot path ------------------------------------------------------ */
+
+/* Plain per-cube FPS-SFT on cube `cube` of the plan: the line gather + FFT
+ * kernel transforms the first chunk of iterations in parallel, then one
+ * work-group peels, tests, decodes and appends iteration by iteration,
+ * gathering and transforming further lines itself when the chunk runs out.
+ * x: device complex64 cube; out: device outputs (see fpssft_out). */
+fpssft_status fpssft_execute(fpssft_plan_t plan, int32_t cube, const void* x,
+                             const fpssft_out* out, void* stream);
+
+/* All cubes of the plan in one persistent launch (work-groups take cubes
+ * from a device queue, longest first), replayed from a HIP graph. xs: host
+ * array of `batch` device cube pointers; outs: host array of `batch` output
+ * structs. Results equal fpssft_execute's cube by cube. */
+fpssft_status fpssft_execute_batched(fpssft_plan_t plan, const void* const* xs,
+                                     const fpssft_out* outs, void* stream);
+
+/* Line gather + L-point DFT (Eq. sample_slice, Eq. hs) of iterations
+ * t0..t0+count-1 of cube `cube`: spectra (device complex64) receives
+ * [count][D+1][L], s_hat(alpha, tau^{(t,i)}, m) with the 1/L factor. */
+fpssft_status fpssft_lines_fft(fpssft_plan_t plan, int32_t cube, const void* x,
+                               int32_t t0, int32_t count, void* spectra,
+                               void* stream);
+
+/* The same for every cube over its whole budget t = 0..T_max-1, in one
+ * launch, into the packed buffer (see fpssft_plan_cube_info). */
+fpssft_status fpssft_lines_fft_all(fpssft_plan_t plan, const void* const* xs,
+                                   void* spectra, void* stream);
+
+/* Adjoint of the amplitude estimates with the decisions of a forward run
+ * held fixed (frequencies, iterations, bins: not differentiated). The
+ * amplitudes are then linear in x, a = M x; this writes grad_x = M^H grad_a
+ * (PyTorch's complex convention: for real l, grad = dl/dRe + j dl/dIm).
+ * fwd: the forward outputs of cube `cube` (records and info on device);
+ * grad_amps: device complex64 [max_k] (entries past k ignored); grad_x:
+ * device complex64 cube, overwritten (zero off the sampled lines). */
+fpssft_status fpssft_amp_backward(fpssft_plan_t plan, int32_t cube,
+                                  const fpssft_out* fwd, const void* grad_amps,
+                                  void* grad_x, void* stream);
+
+/* The adjoint for every cube of the plan in one launch. */
+fpssft_status fpssft_amp_backward_batched(fpssft_plan_t plan,
+                                          const fpssft_out* fwds,
+                                          const void* const* grad_amps,
+                                          void* const* grad_xs, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FPSSFT_H */

@@ -1,0 +1,644 @@
+// Host side of the FPS-SFT C ABI: validation, line schedules, FFT
+// factorisations, twiddle tables, plans (device tables + workspace), the
+// launch sequences of the plain, batched, line-FFT and adjoint entry points,
+// and the HIP graph of the batched path.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <new>
+#include <numeric>
+#include <vector>
+
+#include "../../include/fpssft.h"
+#include "launch.h"
+#include "types.h"
+
+using fpssft::LaunchCtx;
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// Exact integer helpers.
+// ---------------------------------------------------------------------------
+int64_t gcd64(int64_t a, int64_t b) {
+  while (b) {
+    int64_t t = a % b;
+    a = b;
+    b = t;
+  }
+  return a < 0 ? -a : a;
+}
+
+bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
+
+// L = LCM(N_k) (Lemma 1); returns -1 if it exceeds `cap`.
+int64_t lcm_dims(const int32_t* dims, int D, int64_t cap) {
+  int64_t L = 1;
+  for (int k = 0; k < D; ++k) {
+    L = L / gcd64(L, dims[k]) * dims[k];
+    if (L > cap) return -1;
+  }
+  return L;
+}
+
+constexpr int64_t kMaxL = 65536;
+
+// ---------------------------------------------------------------------------
+// SplitMix64 (Steele, Lea, Flood 2014): output i of the stream started at
+// `seed` is the published mix of seed + (i+1) * golden gamma.
+// ---------------------------------------------------------------------------
+uint64_t splitmix64(uint64_t seed, uint64_t i) {
+  uint64_t z = seed + (i + 1) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// floor(z * n / 2^64)
+uint32_t draw_below(uint64_t z, uint32_t n) {
+  return (uint32_t)(((unsigned __int128)z * n) >> 64);
+}
+
+fpssft_status validate(const fpssft_desc* d, int32_t* L_out, int32_t* T_out) {
+  if (!d) return FPSSFT_ERR_INVALID_ARG;
+  if (d->ndim < 1 || d->ndim > FPSSFT_MAX_D) return FPSSFT_ERR_INVALID_ARG;
+  int64_t N = 1;
+  for (int k = 0; k < d->ndim; ++k) {
+    if (d->dims[k] < 1) return FPSSFT_ERR_INVALID_ARG;
+    N *= d->dims[k];
+    if (N >= (int64_t(1) << 40)) return FPSSFT_ERR_UNSUPPORTED;
+  }
+  if (d->max_k < 1 || d->max_iters < 0) return FPSSFT_ERR_INVALID_ARG;
+  if (!std::isfinite(d->zero_thresh) || d->zero_thresh < 0.f) return FPSSFT_ERR_INVALID_ARG;
+  if (!std::isfinite(d->mag_rel_tol) || d->mag_rel_tol < 0.f) return FPSSFT_ERR_INVALID_ARG;
+  if (!std::isfinite(d->grid_tol)) return FPSSFT_ERR_INVALID_ARG;
+  if (d->schedule && d->max_iters == 0) return FPSSFT_ERR_INVALID_ARG;
+  const int64_t L = lcm_dims(d->dims, d->ndim, kMaxL);
+  if (L < 0) return FPSSFT_ERR_UNSUPPORTED;
+  for (int k = 0; k < d->ndim; ++k)
+    if ((int64_t)d->dims[k] * L >= (int64_t(1) << 31)) return FPSSFT_ERR_UNSUPPORTED;
+  int64_t T = d->max_iters;
+  if (T == 0) T = std::max<int64_t>(1, N / ((int64_t)(d->ndim + 1) * L));
+  if (T > (int64_t(1) << 24)) return FPSSFT_ERR_UNSUPPORTED;
+  if (d->schedule) {
+    for (int64_t t = 0; t < T; ++t)
+      for (int s = 0; s < 2; ++s)
+        for (int k = 0; k < d->ndim; ++k) {
+          const int32_t v = d->schedule[(t * 2 + s) * d->ndim + k];
+          if (v < 0 || v >= d->dims[k]) return FPSSFT_ERR_INVALID_ARG;
+        }
+  }
+  if (L_out) *L_out = (int32_t)L;
+  if (T_out) *T_out = (int32_t)T;
+  return FPSSFT_OK;
+}
+
+void generate_schedule(const fpssft_desc* d, int32_t L, int32_t T, int32_t* at) {
+  const int D = d->ndim;
+  uint64_t ctr = 0;
+  for (int32_t t = 0; t < T; ++t) {
+    int32_t* row = at + (int64_t)t * 2 * D;
+    for (;;) {
+      int64_t g = 0;
+      for (int k = 0; k < D; ++k) {
+        row[k] = (int32_t)draw_below(splitmix64(d->seed, ctr++), (uint32_t)d->dims[k]);
+        g = gcd64(g, (int64_t)(L / d->dims[k]) * row[k]);
+      }
+      if (g == 1) break;
+    }
+    for (int k = 0; k < D; ++k)
+      row[D + k] = (int32_t)draw_below(splitmix64(d->seed, ctr++), (uint32_t)d->dims[k]);
+  }
+}
+
+// Stockham stage radices for length L: powers of two in chunks of at most
+// `max_radix`, then odd primes ascending.
+bool factor_fft(int32_t L, int max_radix, int32_t* radix, int32_t* nstages) {
+  int n = L, s = 0;
+  int lg = 0;
+  while ((n & 1) == 0) {
+    n >>= 1;
+    ++lg;
+  }
+  const int lgr = max_radix >= 8 ? 3 : (max_radix >= 4 ? 2 : 1);
+  while (lg > 0) {
+    const int take = std::min(lg, lgr);
+    if (s >= FPSSFT_MAX_STAGES) return false;
+    radix[s++] = 1 << take;
+    lg -= take;
+  }
+  for (int p = 3; n > 1; p += 2) {
+    while (n % p == 0) {
+      if (s >= FPSSFT_MAX_STAGES) return false;
+      radix[s++] = p;
+      n /= p;
+    }
+    if ((int64_t)p * p > n && n > 1) {
+      if (s >= FPSSFT_MAX_STAGES) return false;
+      radix[s++] = n;
+      n = 1;
+    }
+  }
+  *nstages = s;
+  return true;
+}
+
+struct StagedTable {
+  // A device table whose contents follow host arrays of pointers. The
+  // pinned staging copy is reused only after the previous upload from it
+  // has executed.
+  void* dev = nullptr;
+  void* pinned = nullptr;
+  size_t bytes = 0;
+  hipEvent_t done = nullptr;
+  bool valid = false;
+  std::vector<char> last;
+
+  hipError_t init(size_t nbytes) {
+    bytes = nbytes;
+    hipError_t e = hipMalloc(&dev, std::max<size_t>(bytes, 16));
+    if (e != hipSuccess) return e;
+    e = hipHostMalloc(&pinned, std::max<size_t>(bytes, 16), hipHostMallocDefault);
+    if (e != hipSuccess) return e;
+    return hipEventCreateWithFlags(&done, hipEventDisableTiming);
+  }
+  // Upload `src` if it differs from the last upload. Stream-ordered.
+  hipError_t update(const void* src, hipStream_t st) {
+    if (valid && last.size() == bytes && std::memcmp(last.data(), src, bytes) == 0) return hipSuccess;
+    hipError_t e = hipEventSynchronize(done);
+    if (e != hipSuccess) return e;
+    std::memcpy(pinned, src, bytes);
+    e = hipMemcpyAsync(dev, pinned, bytes, hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return e;
+    e = hipEventRecord(done, st);
+    if (e != hipSuccess) return e;
+    last.assign((const char*)src, (const char*)src + bytes);
+    valid = true;
+    return hipSuccess;
+  }
+  void release() {
+    if (done) hipEventSynchronize(done), hipEventDestroy(done);
+    if (dev) hipFree(dev);
+    if (pinned) hipHostFree(pinned);
+    dev = pinned = nullptr;
+    done = nullptr;
+  }
+};
+
+fpssft_status hip_status(hipError_t e) {
+  if (e == hipSuccess) return FPSSFT_OK;
+  if (e == hipErrorOutOfMemory) return FPSSFT_ERR_NOMEM;
+  if (e == hipErrorNoDevice || e == hipErrorInvalidDevice) return FPSSFT_ERR_NO_DEVICE;
+  if (std::getenv("FPSSFT_LOG")) std::fprintf(stderr, "fpssft: HIP error %s\n", hipGetErrorString(e));
+  return FPSSFT_ERR_HIP;
+}
+
+#define HIP_TRY(expr)                                   \
+  do {                                                  \
+    hipError_t _e = (expr);                             \
+    if (_e != hipSuccess) return hip_status(_e);        \
+  } while (0)
+
+}  // namespace
+
+struct fpssft_plan_st {
+  int device = 0;
+  int B = 0;
+  int ncu = 0;
+  size_t lds_max = 0;
+  fpssft_tuning tune{};
+  std::vector<CubeDesc> descs;
+  std::vector<int32_t> sched;
+  std::vector<float2> tw;
+  int64_t spec_elems = 0;
+  LaunchCtx ctx{};
+  CubeDesc* d_descs = nullptr;
+  int32_t* d_sched = nullptr;
+  float2* d_tw = nullptr;
+  // plain path
+  float2* d_pre = nullptr;
+  int32_t pre_iters = 0;
+  int32_t lines_G_single = 1;
+  size_t lds_lines_single = 0;
+  size_t lds_solve = 0;
+  size_t lds_bwd = 0;
+  // batched path
+  int32_t* d_order = nullptr;
+  int* d_queue = nullptr;
+  int grid_batched = 0;
+  StagedTable xs_tab, outs_tab, ga_tab, gx_tab, len_tab;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  hipStream_t cap_stream = nullptr;
+  // line-FFT over the whole budget
+  std::vector<LineItem> items;
+  LineItem* d_items = nullptr;
+  size_t lds_lines_all = 0;
+  int64_t max_N = 0;
+  int32_t maxL = 1;
+  int32_t maxD = 1;
+};
+
+namespace {
+
+size_t solve_lds_bytes(const CubeDesc& c, int rec_lds) {
+  size_t b = 2 * (size_t)(c.D + 1) * c.L * sizeof(float2);
+  b += (size_t)rec_lds * sizeof(float2) + (size_t)rec_lds * c.D * sizeof(int32_t);
+  b += 64 * sizeof(int);
+  return b;
+}
+
+size_t bwd_lds_bytes(const CubeDesc& c) {
+  return 2 * (size_t)c.L * sizeof(float2) + (size_t)c.max_k * sizeof(float2) + 64;
+}
+
+int lines_group(const CubeDesc& c, int lines_wg, size_t lds_max) {
+  int G = std::max(1, lines_wg / (c.D + 1));
+  while (G > 1 && 2 * (size_t)G * (c.D + 1) * c.L * sizeof(float2) > lds_max) --G;
+  return G;
+}
+
+void destroy_plan(fpssft_plan_t p) {
+  if (!p) return;
+  hipSetDevice(p->device);
+  hipDeviceSynchronize();
+  if (p->gexec) hipGraphExecDestroy(p->gexec);
+  if (p->graph) hipGraphDestroy(p->graph);
+  if (p->cap_stream) hipStreamDestroy(p->cap_stream);
+  p->xs_tab.release();
+  p->outs_tab.release();
+  p->ga_tab.release();
+  p->gx_tab.release();
+  p->len_tab.release();
+  hipFree(p->d_descs);
+  hipFree(p->d_sched);
+  hipFree(p->d_tw);
+  hipFree(p->d_pre);
+  hipFree(p->d_order);
+  hipFree(p->d_queue);
+  hipFree(p->d_items);
+  delete p;
+}
+
+fpssft_status build_plan(const fpssft_desc* descs, int32_t batch, const fpssft_tuning* tuning,
+                         fpssft_plan_t p) {
+  HIP_TRY(hipGetDevice(&p->device));
+  int v = 0;
+  HIP_TRY(hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, p->device));
+  p->ncu = v;
+  HIP_TRY(hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, p->device));
+  // Dynamic LDS budget; 1 KiB stays for the kernels' static __shared__ data.
+  if (v <= 2048) return FPSSFT_ERR_UNSUPPORTED;
+  p->lds_max = (size_t)v - 1024;
+  p->B = batch;
+  fpssft_tuning tn{256, 8, 8, 16};
+  if (tuning) {
+    if (tuning->block_threads) tn.block_threads = tuning->block_threads;
+    if (tuning->max_radix) tn.max_radix = tuning->max_radix;
+    if (tuning->chunk_iters >= 0) tn.chunk_iters = tuning->chunk_iters;
+    if (tuning->lines_wg) tn.lines_wg = tuning->lines_wg;
+  }
+  if (tn.block_threads < 64 || tn.block_threads > 1024 || tn.block_threads % 64) return FPSSFT_ERR_INVALID_ARG;
+  if (tn.max_radix != 2 && tn.max_radix != 4 && tn.max_radix != 8) return FPSSFT_ERR_INVALID_ARG;
+  if (tn.lines_wg < 1) return FPSSFT_ERR_INVALID_ARG;
+  p->tune = tn;
+
+  std::map<int32_t, int32_t> tw_off;
+  p->descs.resize(batch);
+  int32_t max_pre_elems_T = 0;
+  int64_t max_pre = 0;
+  for (int32_t c = 0; c < batch; ++c) {
+    const fpssft_desc& d = descs[c];
+    int32_t L, T;
+    fpssft_status st = validate(&d, &L, &T);
+    if (st != FPSSFT_OK) return st;
+    CubeDesc cd{};
+    cd.D = d.ndim;
+    cd.L = L;
+    cd.T = T;
+    cd.max_k = d.max_k;
+    int64_t stride = 1;
+    for (int k = d.ndim - 1; k >= 0; --k) {
+      cd.stride[k] = stride;
+      stride *= d.dims[k];
+    }
+    cd.N = stride;
+    for (int k = 0; k < 4; ++k) {
+      cd.dims[k] = k < d.ndim ? d.dims[k] : 1;
+      cd.c[k] = k < d.ndim ? L / d.dims[k] : 1;
+      cd.dmask[k] = (k < d.ndim && is_pow2(d.dims[k])) ? d.dims[k] - 1 : -1;
+      if (k >= d.ndim) cd.stride[k] = 0;
+    }
+    cd.Lmask = is_pow2(L) ? L - 1 : -1;
+    if (!factor_fft(L, tn.max_radix, cd.radix, &cd.nstages)) return FPSSFT_ERR_UNSUPPORTED;
+    cd.inv_L = (float)(1.0 / (double)L);
+    cd.zero_thresh = d.zero_thresh;
+    cd.mag_rel_tol = d.mag_rel_tol;
+    cd.grid_tol = d.grid_tol;
+    cd.sched_off = (int32_t)p->sched.size();
+    if ((int64_t)p->sched.size() + (int64_t)T * 2 * d.ndim >= (int64_t(1) << 31)) return FPSSFT_ERR_UNSUPPORTED;
+    p->sched.resize(p->sched.size() + (size_t)T * 2 * d.ndim);
+    if (d.schedule)
+      std::memcpy(p->sched.data() + cd.sched_off, d.schedule, sizeof(int32_t) * T * 2 * d.ndim);
+    else
+      generate_schedule(&d, L, T, p->sched.data() + cd.sched_off);
+    auto it = tw_off.find(L);
+    if (it == tw_off.end()) {
+      const int32_t off = (int32_t)p->tw.size();
+      for (int32_t k = 0; k < L; ++k) {
+        const double ang = -2.0 * M_PI * (double)k / (double)L;
+        p->tw.push_back(make_float2((float)std::cos(ang), (float)std::sin(ang)));
+      }
+      it = tw_off.emplace(L, off).first;
+    }
+    cd.tw_off = it->second;
+    // Records in LDS when spectra + records fit; otherwise the output arrays.
+    cd.rec_lds = solve_lds_bytes(cd, cd.max_k) <= p->lds_max ? cd.max_k : 0;
+    if (solve_lds_bytes(cd, cd.rec_lds) > p->lds_max) return FPSSFT_ERR_UNSUPPORTED;
+    cd.spec_off = p->spec_elems;
+    p->spec_elems += (int64_t)T * (d.ndim + 1) * L;
+    const int32_t pre_T = std::min(T, tn.chunk_iters);
+    max_pre = std::max<int64_t>(max_pre, (int64_t)pre_T * (d.ndim + 1) * L);
+    max_pre_elems_T = std::max(max_pre_elems_T, pre_T);
+    p->lds_solve = std::max(p->lds_solve, solve_lds_bytes(cd, cd.rec_lds));
+    p->lds_bwd = std::max(p->lds_bwd, bwd_lds_bytes(cd));
+    p->max_N = std::max(p->max_N, cd.N);
+    p->maxL = std::max(p->maxL, L);
+    p->maxD = std::max(p->maxD, (int32_t)d.ndim);
+    p->descs[c] = cd;
+  }
+  // Line-FFT work-group shapes: one G for single-cube calls (largest cube),
+  // per-cube G in the all-cubes item list.
+  {
+    CubeDesc worst{};
+    worst.D = p->maxD;
+    worst.L = p->maxL;
+    p->lines_G_single = lines_group(worst, tn.lines_wg, p->lds_max);
+    p->lds_lines_single = 2 * (size_t)p->lines_G_single * (p->maxD + 1) * p->maxL * sizeof(float2);
+    if (p->lds_lines_single > p->lds_max) return FPSSFT_ERR_UNSUPPORTED;
+  }
+  for (int32_t c = 0; c < batch; ++c) {
+    const CubeDesc& cd = p->descs[c];
+    const int G = lines_group(cd, tn.lines_wg, p->lds_max);
+    p->lds_lines_all = std::max(p->lds_lines_all, 2 * (size_t)G * (cd.D + 1) * cd.L * sizeof(float2));
+    for (int32_t t = 0; t < cd.T; t += G) {
+      LineItem li{};
+      li.cube = c;
+      li.t0 = t;
+      li.count = std::min(G, cd.T - t);
+      li.out_off = cd.spec_off + (int64_t)t * (cd.D + 1) * cd.L;
+      p->items.push_back(li);
+    }
+  }
+  p->pre_iters = max_pre_elems_T;
+
+  HIP_TRY(hipMalloc(&p->d_descs, sizeof(CubeDesc) * batch));
+  HIP_TRY(hipMemcpy(p->d_descs, p->descs.data(), sizeof(CubeDesc) * batch, hipMemcpyHostToDevice));
+  HIP_TRY(hipMalloc(&p->d_sched, sizeof(int32_t) * std::max<size_t>(p->sched.size(), 1)));
+  HIP_TRY(hipMemcpy(p->d_sched, p->sched.data(), sizeof(int32_t) * p->sched.size(), hipMemcpyHostToDevice));
+  HIP_TRY(hipMalloc(&p->d_tw, sizeof(float2) * p->tw.size()));
+  HIP_TRY(hipMemcpy(p->d_tw, p->tw.data(), sizeof(float2) * p->tw.size(), hipMemcpyHostToDevice));
+  if (max_pre > 0) HIP_TRY(hipMalloc(&p->d_pre, sizeof(float2) * max_pre));
+  // Batched order: longest lines first (the per-iteration cost grows with
+  // (D+1) L), ties by index.
+  std::vector<int32_t> order(batch);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+    const int64_t ca = (int64_t)(p->descs[a].D + 1) * p->descs[a].L;
+    const int64_t cb = (int64_t)(p->descs[b].D + 1) * p->descs[b].L;
+    return ca > cb;
+  });
+  HIP_TRY(hipMalloc(&p->d_order, sizeof(int32_t) * batch));
+  HIP_TRY(hipMemcpy(p->d_order, order.data(), sizeof(int32_t) * batch, hipMemcpyHostToDevice));
+  HIP_TRY(hipMalloc(&p->d_queue, sizeof(int) * 4));
+  HIP_TRY(hipMemset(p->d_queue, 0, sizeof(int) * 4));
+  HIP_TRY(hipMalloc(&p->d_items, sizeof(LineItem) * std::max<size_t>(p->items.size(), 1)));
+  HIP_TRY(hipMemcpy(p->d_items, p->items.data(), sizeof(LineItem) * p->items.size(), hipMemcpyHostToDevice));
+  HIP_TRY(p->xs_tab.init(sizeof(void*) * batch));
+  HIP_TRY(p->outs_tab.init(sizeof(OutPtrs) * batch));
+  HIP_TRY(p->ga_tab.init(sizeof(void*) * batch));
+  HIP_TRY(p->gx_tab.init(sizeof(void*) * batch));
+  HIP_TRY(p->len_tab.init(sizeof(int64_t) * batch));
+  p->ctx.descs = p->d_descs;
+  p->ctx.sched = p->d_sched;
+  p->ctx.tw = p->d_tw;
+
+  const int threads = tn.block_threads;
+  for (const void* fn : {fpssft::kernel_solve_batched(), fpssft::kernel_solve_plain(), fpssft::kernel_lines(),
+                         fpssft::kernel_backward()}) {
+    HIP_TRY(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p->lds_max));
+  }
+  int occ = 0;
+  HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fpssft::kernel_solve_batched(), threads,
+                                                       p->lds_solve));
+  if (occ < 1) return FPSSFT_ERR_UNSUPPORTED;
+  p->grid_batched = std::min<int64_t>(batch, (int64_t)occ * p->ncu);
+  if (p->grid_batched < 1) p->grid_batched = 1;
+  HIP_TRY(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
+  return FPSSFT_OK;
+}
+
+bool check_out(const fpssft_out* o) {
+  return o && o->freqs && o->amps && o->rec_iter && o->rec_bin && o->info;
+}
+
+OutPtrs to_ptrs(const fpssft_out& o) {
+  OutPtrs p;
+  p.freqs = o.freqs;
+  p.amps = o.amps;
+  p.rec_iter = o.rec_iter;
+  p.rec_bin = o.rec_bin;
+  p.info = o.info;
+  return p;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* fpssft_strerror(int32_t s) {
+  switch (s) {
+    case FPSSFT_OK: return "ok";
+    case FPSSFT_INCOMPLETE: return "incomplete: iteration budget reached with a nonzero residual";
+    case FPSSFT_CAPACITY: return "capacity: the record list is full";
+    case FPSSFT_ERR_INVALID_ARG: return "invalid argument";
+    case FPSSFT_ERR_UNSUPPORTED: return "unsupported size for this build";
+    case FPSSFT_ERR_HIP: return "HIP runtime error";
+    case FPSSFT_ERR_NOMEM: return "out of device memory";
+    case FPSSFT_ERR_NO_DEVICE: return "no HIP device";
+    default: return "unknown status";
+  }
+}
+
+int32_t fpssft_abi_version(void) { return FPSSFT_ABI_VERSION; }
+
+fpssft_status fpssft_validate(const fpssft_desc* desc, int32_t* line_length, int32_t* max_iters) {
+  return validate(desc, line_length, max_iters);
+}
+
+fpssft_status fpssft_schedule_generate(const fpssft_desc* desc, int32_t T, int32_t* alpha_tau) {
+  int32_t L, Tm;
+  fpssft_desc d = *desc;
+  d.schedule = nullptr;
+  fpssft_status st = validate(&d, &L, &Tm);
+  if (st != FPSSFT_OK) return st;
+  if (T < 0 || (T > 0 && !alpha_tau)) return FPSSFT_ERR_INVALID_ARG;
+  generate_schedule(&d, L, T, alpha_tau);
+  return FPSSFT_OK;
+}
+
+fpssft_status fpssft_plan_create(const fpssft_desc* descs, int32_t batch, const fpssft_tuning* tuning,
+                                 fpssft_plan_t* plan) {
+  if (!descs || batch < 1 || !plan) return FPSSFT_ERR_INVALID_ARG;
+  *plan = nullptr;
+  for (int32_t c = 0; c < batch; ++c) {
+    fpssft_status st = validate(&descs[c], nullptr, nullptr);
+    if (st != FPSSFT_OK) return st;
+  }
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return FPSSFT_ERR_NO_DEVICE;
+  fpssft_plan_t p = new (std::nothrow) fpssft_plan_st();
+  if (!p) return FPSSFT_ERR_NOMEM;
+  fpssft_status st = build_plan(descs, batch, tuning, p);
+  if (st != FPSSFT_OK) {
+    destroy_plan(p);
+    return st;
+  }
+  *plan = p;
+  return FPSSFT_OK;
+}
+
+fpssft_status fpssft_plan_destroy(fpssft_plan_t plan) {
+  if (!plan) return FPSSFT_ERR_INVALID_ARG;
+  destroy_plan(plan);
+  return FPSSFT_OK;
+}
+
+fpssft_status fpssft_plan_get_schedule(fpssft_plan_t p, int32_t cube, int32_t* alpha_tau) {
+  if (!p || cube < 0 || cube >= p->B || !alpha_tau) return FPSSFT_ERR_INVALID_ARG;
+  const CubeDesc& cd = p->descs[cube];
+  std::memcpy(alpha_tau, p->sched.data() + cd.sched_off, sizeof(int32_t) * cd.T * 2 * cd.D);
+  return FPSSFT_OK;
+}
+
+fpssft_status fpssft_plan_cube_info(fpssft_plan_t p, int32_t cube, int32_t* line_length, int32_t* max_iters,
+                                    int64_t* spectra_offset) {
+  if (!p || cube < 0 || cube >= p->B) return FPSSFT_ERR_INVALID_ARG;
+  const CubeDesc& cd = p->descs[cube];
+  if (line_length) *line_length = cd.L;
+  if (max_iters) *max_iters = cd.T;
+  if (spectra_offset) *spectra_offset = cd.spec_off;
+  return FPSSFT_OK;
+}
+
+int64_t fpssft_plan_spectra_elems(fpssft_plan_t p) { return p ? p->spec_elems : -1; }
+
+fpssft_status fpssft_execute(fpssft_plan_t p, int32_t cube, const void* x, const fpssft_out* out,
+                             void* stream) {
+  if (!p || cube < 0 || cube >= p->B || !x || !check_out(out)) return FPSSFT_ERR_INVALID_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  const CubeDesc& cd = p->descs[cube];
+  const int pre = std::min(cd.T, p->tune.chunk_iters);
+  if (pre > 0) {
+    HIP_TRY(fpssft::launch_lines_single(p->ctx, cube, (const float2*)x, 0, pre, p->lines_G_single, p->d_pre,
+                                        p->lds_lines_single, p->tune.block_threads, st));
+  }
+  HIP_TRY(fpssft::launch_solve_plain(p->ctx, cube, (const float2*)x, to_ptrs(*out), p->d_pre, pre, p->lds_solve,
+                                     p->tune.block_threads, st));
+  return FPSSFT_OK;
+}
+
+fpssft_status fpssft_execute_batched(fpssft_plan_t p, const void* const* xs, const fpssft_out* outs,
+                                     void* stream) {
+  if (!p || !xs || !outs) return FPSSFT_ERR_INVALID_ARG;
+  std::vector<OutPtrs> op(p->B);
+  for (int c = 0; c < p->B; ++c) {
+    if (!xs[c] || !check_out(&outs[c])) return FPSSFT_ERR_INVALID_ARG;
+    op[c] = to_ptrs(outs[c]);
+  }
+  hipStream_t st = (hipStream_t)stream;
+  HIP_TRY(p->xs_tab.update(xs, st));
+  HIP_TRY(p->outs_tab.update(op.data(), st));
+  if (!p->gexec) {
+    HIP_TRY(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
+    hipError_t e = fpssft::launch_solve_batched(p->ctx, (const float2* const*)p->xs_tab.dev,
+                                                (const OutPtrs*)p->outs_tab.dev, p->d_order, p->B, p->d_queue,
+                                                p->grid_batched, p->lds_solve, p->tune.block_threads,
+                                                p->cap_stream);
+    hipGraph_t g = nullptr;
+    hipError_t e2 = hipStreamEndCapture(p->cap_stream, &g);
+    if (e != hipSuccess) return hip_status(e);
+    if (e2 != hipSuccess) return hip_status(e2);
+    p->graph = g;
+    HIP_TRY(hipGraphInstantiate(&p->gexec, p->graph, nullptr, nullptr, 0));
+  }
+  HIP_TRY(hipGraphLaunch(p->gexec, st));
+  return FPSSFT_OK;
+}
+
+fpssft_status fpssft_lines_fft(fpssft_plan_t p, int32_t cube, const void* x, int32_t t0, int32_t count,
+                               void* spectra, void* stream) {
+  if (!p || cube < 0 || cube >= p->B || !x || !spectra) return FPSSFT_ERR_INVALID_ARG;
+  const CubeDesc& cd = p->descs[cube];
+  if (t0 < 0 || count < 0 || (int64_t)t0 + count > cd.T) return FPSSFT_ERR_INVALID_ARG;
+  if (count == 0) return FPSSFT_OK;
+  HIP_TRY(fpssft::launch_lines_single(p->ctx, cube, (const float2*)x, t0, count, p->lines_G_single,
+                                      (float2*)spectra, p->lds_lines_single, p->tune.block_threads,
+                                      (hipStream_t)stream));
+  return FPSSFT_OK;
+}
+
+fpssft_status fpssft_lines_fft_all(fpssft_plan_t p, const void* const* xs, void* spectra, void* stream) {
+  if (!p || !xs || !spectra) return FPSSFT_ERR_INVALID_ARG;
+  for (int c = 0; c < p->B; ++c)
+    if (!xs[c]) return FPSSFT_ERR_INVALID_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  HIP_TRY(p->xs_tab.update(xs, st));
+  HIP_TRY(fpssft::launch_lines_items(p->ctx, p->d_items, (int)p->items.size(),
+                                     (const float2* const*)p->xs_tab.dev, (float2*)spectra, p->lds_lines_all,
+                                     p->tune.block_threads, st));
+  return FPSSFT_OK;
+}
+
+fpssft_status fpssft_amp_backward(fpssft_plan_t p, int32_t cube, const fpssft_out* fwd, const void* grad_amps,
+                                  void* grad_x, void* stream) {
+  if (!p || cube < 0 || cube >= p->B || !check_out(fwd) || !grad_amps || !grad_x) return FPSSFT_ERR_INVALID_ARG;
+  if (p->lds_bwd > p->lds_max) return FPSSFT_ERR_UNSUPPORTED;
+  hipStream_t st = (hipStream_t)stream;
+  const CubeDesc& cd = p->descs[cube];
+  HIP_TRY(fpssft::launch_zero_single((float2*)grad_x, cd.N, st));
+  HIP_TRY(fpssft::launch_backward_single(p->ctx, cube, to_ptrs(*fwd), (const float2*)grad_amps,
+                                         (float2*)grad_x, p->lds_bwd, p->tune.block_threads, st));
+  return FPSSFT_OK;
+}
+
+fpssft_status fpssft_amp_backward_batched(fpssft_plan_t p, const fpssft_out* fwds, const void* const* grad_amps,
+                                          void* const* grad_xs, void* stream) {
+  if (!p || !fwds || !grad_amps || !grad_xs) return FPSSFT_ERR_INVALID_ARG;
+  if (p->lds_bwd > p->lds_max) return FPSSFT_ERR_UNSUPPORTED;
+  std::vector<OutPtrs> op(p->B);
+  std::vector<int64_t> lens(p->B);
+  for (int c = 0; c < p->B; ++c) {
+    if (!check_out(&fwds[c]) || !grad_amps[c] || !grad_xs[c]) return FPSSFT_ERR_INVALID_ARG;
+    op[c] = to_ptrs(fwds[c]);
+    lens[c] = p->descs[c].N;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  HIP_TRY(p->outs_tab.update(op.data(), st));
+  HIP_TRY(p->ga_tab.update(grad_amps, st));
+  HIP_TRY(p->gx_tab.update(grad_xs, st));
+  HIP_TRY(p->len_tab.update(lens.data(), st));
+  HIP_TRY(fpssft::launch_zero_multi((float2* const*)p->gx_tab.dev, (const int64_t*)p->len_tab.dev, p->B,
+                                    p->max_N, st));
+  HIP_TRY(fpssft::launch_backward_batched(p->ctx, p->B, (const OutPtrs*)p->outs_tab.dev,
+                                          (const float2* const*)p->ga_tab.dev, (float2* const*)p->gx_tab.dev,
+                                          p->lds_bwd, p->tune.block_threads, st));
+  return FPSSFT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,50 @@
+// Plain-old-data tables shared by the host plan and the gfx950 kernels.
+#pragma once
+#include <stdint.h>
+
+#define FPSSFT_MAX_STAGES 24
+
+// Everything a kernel needs to know about one cube. Built on the host,
+// uploaded once per plan, read through scalar loads on the device.
+struct CubeDesc {
+  int32_t D;                 // dimensions
+  int32_t L;                 // line length LCM(N_k) (Lemma 1)
+  int32_t T;                 // iteration budget T_max
+  int32_t max_k;             // record capacity
+  int32_t dims[4];           // N_k
+  int32_t c[4];              // c_k = L / N_k
+  int32_t dmask[4];          // N_k - 1 when N_k is a power of two, else -1
+  int64_t stride[4];         // element strides, last dimension contiguous
+  int64_t N;                 // total elements
+  int32_t Lmask;             // L - 1 when L is a power of two, else -1
+  int32_t nstages;           // FFT stages
+  int32_t radix[FPSSFT_MAX_STAGES];
+  float inv_L;
+  float zero_thresh;         // theta0
+  float mag_rel_tol;         // rho
+  float grid_tol;            // gamma (< 0: off)
+  int32_t sched_off;         // int32 offset of [T][2][D] in the schedule table
+  int32_t tw_off;            // float2 offset of W_L in the twiddle table
+  int32_t rec_lds;           // records kept in LDS (capacity), 0: global
+  int32_t pad0;
+  int64_t spec_off;          // element offset in the packed spectra buffer
+};
+
+// Device pointers of one cube's outputs (same layout as fpssft_out).
+struct OutPtrs {
+  int32_t* freqs;
+  void* amps;
+  int32_t* rec_iter;
+  int32_t* rec_bin;
+  int32_t* info;
+};
+
+// One work item of the line gather + FFT kernel: `count` iterations of one
+// cube starting at t0, written at element offset `out_off`.
+struct LineItem {
+  int32_t cube;
+  int32_t t0;
+  int32_t count;
+  int32_t pad;
+  int64_t out_off;
+};

@@ -1,0 +1,98 @@
+"""Adjoint of the amplitude estimates (decisions fixed) on the GPU against
+the FP64 finite-difference gradient of the oracle's replayed amplitudes."""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from gpu_common import compare, log, oracle_for, spec_for, torch_dev
+
+pytestmark = pytest.mark.gpu
+
+GRAD_TOL = 1e-4
+
+
+@pytest.fixture(scope="module")
+def F():
+    import paper_1711_11407_amd as F
+    return F
+
+
+def fd_reference(cube_x, ref, al, ta):
+    x64 = cube_x.astype(np.complex128)
+    pos = O.touched_positions(cube_x.shape, ref.rec_iter, al, ta)
+    g = O.grad_sum_abs2_fd(x64, ref, al, ta, positions=pos)
+    return g, pos
+
+
+@pytest.mark.parametrize("dims,K,seed,T", [((64, 64), 40, 3, 30), ((16, 24), 20, 4, 30),
+                                           ((8, 8, 12), 30, 5, 40), ((256, 256), 50, 6, 0)])
+def test_amp_backward_matches_fd(F, dims, K, seed, T):
+    torch, dev = torch_dev()
+    cube = W.plant(dims, K, seed=seed)
+    spec = spec_for(F, dims, seed + 1, max_iters=T, max_k=256)
+    plan = F.Plan([spec])
+    x = torch.from_numpy(cube.x).to(dev).requires_grad_(True)
+    amps, freqs, info = F.sft_amplitudes(plan, 0, x)
+    loss = (amps.abs() ** 2).sum()
+    loss.backward()
+    g = x.grad.cpu().numpy().astype(np.complex128)
+    ref, al, ta = oracle_for(plan, 0, cube.x, spec)
+    k = int(info[0].item())
+    assert k == ref.k
+    gref, pos = fd_reference(cube.x, ref, al, ta)
+    err = np.linalg.norm(g - gref) / np.linalg.norm(gref)
+    log(f"adjoint {dims} K={K}: k={k}, {len(pos)} touched samples, grad rel L2 err={err:.2e}")
+    assert err <= GRAD_TOL
+    mask = np.ones(g.size, bool)
+    mask[pos] = False
+    assert np.all(g.reshape(-1)[mask] == 0)
+
+
+def test_dot_product_identity(F):
+    """<M x, y> = <x, M^H y> with M applied by the GPU forward (decisions of
+    one run held: x is a small perturbation-free scaling of the input) and
+    M^H by the adjoint kernel."""
+    torch, dev = torch_dev()
+    dims = (128, 128)
+    cube = W.plant(dims, 60, seed=8)
+    spec = spec_for(F, dims, 9, max_k=128)
+    plan = F.Plan([spec])
+    x = torch.from_numpy(cube.x).to(dev)
+    res = plan.execute(0, x)
+    h = res.host()
+    rng = np.random.default_rng(1)
+    y = (rng.standard_normal(spec.max_k) + 1j * rng.standard_normal(spec.max_k)).astype(np.complex64)
+    y[h["k"]:] = 0
+    xt = plan.amp_backward(0, res, torch.from_numpy(y).to(dev)).cpu().numpy().astype(np.complex128)
+    lhs = np.vdot(y[:h["k"]].astype(np.complex128), h["amps"].astype(np.complex128))   # <y, Mx>
+    rhs = np.vdot(xt.reshape(-1), cube.x.reshape(-1).astype(np.complex128))            # <M^H y, x>
+    assert abs(lhs - rhs) / abs(lhs) < 1e-5
+
+
+def test_cfg5_batched_backward(F):
+    """Differentiation workload: 64 cubes of 256x256, K=50; batched forward
+    and backward; every cube's gradient equals the single-cube adjoint, and
+    a sample is checked against the FP64 finite differences."""
+    torch, dev = torch_dev()
+    cubes = W.cfg5()
+    specs = [spec_for(F, c.dims, c.schedule_seed, max_k=128) for c in cubes]
+    plan = F.Plan(specs)
+    xs = [torch.from_numpy(c.x).to(dev).requires_grad_(True) for c in cubes]
+    outs = F.sft_amplitudes_batched(plan, xs)
+    loss = sum((a.abs() ** 2).sum() for a, _, _ in outs)
+    loss.backward()
+    for c in (0, 17, 63):
+        ref, al, ta = oracle_for(plan, c, cubes[c].x, specs[c])
+        a, f, info = outs[c]
+        got = dict(k=int(info[0]), iters=int(info[1]), status=int(info[2]),
+                   freqs=f[:int(info[0])].cpu().numpy(), amps=a[:int(info[0])].detach().cpu().numpy(),
+                   rec_iter=ref.rec_iter, rec_bin=ref.rec_bin)
+        compare(got, ref, f"cfg5 cube {c}")
+        gref, _ = fd_reference(cubes[c].x, ref, al, ta)
+        g = xs[c].grad.cpu().numpy().astype(np.complex128)
+        err = np.linalg.norm(g - gref) / np.linalg.norm(gref)
+        assert err <= GRAD_TOL, (c, err)
+        single = plan.execute(c, xs[c].detach())
+        g1 = plan.amp_backward(c, single, 2 * single.amps).cpu().numpy()
+        np.testing.assert_allclose(g1, g, rtol=0, atol=1e-5 * np.abs(g).max())

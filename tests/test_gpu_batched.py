@@ -1,0 +1,109 @@
+"""Batched persistent path (one graph launch for many uneven cubes) against
+the plain path and the FP64 oracle."""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from gpu_common import compare, log, oracle_for, spec_for, torch_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def F():
+    import paper_1711_11407_amd as F
+    return F
+
+
+def batched_setup(F, cubes, max_k=512, tuning=None):
+    torch, dev = torch_dev()
+    specs = [spec_for(F, c.dims, c.schedule_seed, max_k=max_k) for c in cubes]
+    plan = F.Plan(specs, tuning=tuning)
+    xs = [torch.from_numpy(c.x).to(dev) for c in cubes]
+    return plan, specs, xs
+
+
+def test_batched_small_mixed_equals_oracle(F):
+    cubes = [W.plant(d, k, seed=s, mag=(0.5, 1.5)) for d, k, s in
+             [((64, 64), 30, 1), ((16, 24), 10, 2), ((128, 128, 128), 200, 3), ((6, 10), 2, 4),
+              ((512, 64), 120, 5), ((8, 8, 12), 15, 6), ((256, 256), 1000, 7)]]
+    specs = []
+    for c in cubes:
+        T = max(O.default_max_iters(c.dims), 30) if np.prod(c.dims) < 4096 else 0
+        specs.append(spec_for(F, c.dims, c.schedule_seed, max_k=2048, max_iters=T))
+    torch, dev = torch_dev()
+    plan = F.Plan(specs)
+    xs = [torch.from_numpy(c.x).to(dev) for c in cubes]
+    outs = plan.execute_batched(xs)
+    for i, (c, o) in enumerate(zip(cubes, outs)):
+        ref, _, _ = oracle_for(plan, i, c.x, specs[i])
+        compare(o.host(), ref, f"cube {i} {c.dims}")
+
+
+def test_batched_graph_replays_are_stable(F):
+    cubes = W.cfg4(B=48, seed=4)
+    plan, specs, xs = batched_setup(F, cubes)
+    torch, _ = torch_dev()
+    outs = plan.execute_batched(xs)
+    first = [o.host() for o in outs]
+    for rep in range(3):
+        # eager work between replays, then replay into the same outputs
+        for o in outs:
+            o.info.zero_()
+            o.freqs.fill_(-1)
+        torch.cuda.synchronize()
+        plan.execute_batched(xs, outs)
+        for a, o in zip(first, outs):
+            b = o.host()
+            assert a["k"] == b["k"] and a["iters"] == b["iters"] and a["status"] == b["status"]
+            np.testing.assert_array_equal(a["freqs"], b["freqs"])
+            np.testing.assert_allclose(a["amps"], b["amps"], rtol=0, atol=1e-5)
+    # new output buffers re-upload the pointer table
+    outs2 = plan.execute_batched(xs)
+    for a, o in zip(first, outs2):
+        np.testing.assert_array_equal(a["freqs"], o.host()["freqs"])
+
+
+def test_cfg4_full_batch_parity(F):
+    """The full 1024-cube workload in the launch shape the benchmark times:
+    batched equals plain on every cube; the oracle checks a sample."""
+    log("generating cfg4 (1024 cubes)")
+    cubes = W.cfg4()
+    plan, specs, xs = batched_setup(F, cubes)
+    torch, dev = torch_dev()
+    log("batched execute")
+    bout = plan.execute_batched(xs)
+    torch.cuda.synchronize()
+    log("plain execute x1024")
+    pouts = [plan.execute(c, xs[c]) for c in range(len(cubes))]
+    torch.cuda.synchronize()
+    n_ok = 0
+    worst = 0.0
+    for c in range(len(cubes)):
+        b, p = bout[c].host(), pouts[c].host()
+        assert (b["k"], b["iters"], b["status"]) == (p["k"], p["iters"], p["status"]), c
+        np.testing.assert_array_equal(b["freqs"], p["freqs"])
+        np.testing.assert_array_equal(b["rec_bin"], p["rec_bin"])
+        if b["k"]:
+            worst = max(worst, np.linalg.norm(b["amps"] - p["amps"]) / np.linalg.norm(p["amps"]))
+        n_ok += b["status"] == O.STATUS_OK
+    assert worst < 1e-5
+    log(f"cfg4: {n_ok}/1024 reached an empty residual; batched vs plain amp err {worst:.1e}")
+    rng = np.random.default_rng(0)
+    sample = sorted(rng.choice(len(cubes), 48, replace=False).tolist())
+    for c in sample:
+        ref, _, _ = oracle_for(plan, c, cubes[c].x, specs[c])
+        compare(bout[c].host(), ref, f"cfg4 cube {c} {cubes[c].dims}")
+        if ref.status == O.STATUS_OK:
+            assert {tuple(f) for f in ref.freqs.tolist()} == {tuple(f) for f in cubes[c].freqs.tolist()}
+
+
+@pytest.mark.parametrize("tuning", [dict(block_threads=128), dict(block_threads=512, max_radix=4)])
+def test_batched_launch_shapes_agree(F, tuning):
+    cubes = W.cfg4(B=40, seed=9)
+    plan, specs, xs = batched_setup(F, cubes, tuning=tuning)
+    outs = plan.execute_batched(xs)
+    for c in range(0, 40, 5):
+        ref, _, _ = oracle_for(plan, c, cubes[c].x, specs[c])
+        compare(outs[c].host(), ref, f"{tuning} cube {c}")
