@@ -1,0 +1,269 @@
+"""Benchmark of the FPS-SFT hot path on one MI355X.
+
+Workload (one step): the batched workload of 1024 independent 2-D complex64
+cubes, sides drawn iid from {64, 128, 256, 512}, K ~ U{10..300} on-grid
+sinusoids of unit magnitude and random phase, noiseless (seed 4), recovered
+by one persistent launch replayed from a HIP graph. Inputs are resident in
+HBM before the timed region.
+
+Printed as one JSON line:
+  value         batched sparse transforms/s (1024 / step time)
+  roofline      the step's dominant kernel (the persistent solve kernel):
+                algorithmic bytes per launch / launch time vs 8 TB/s
+  line_fft      the line gather + FFT kernel over every cube's whole
+                iteration budget (about 100% of the samples): HBM GB/s
+  plain         1024 plain per-cube launches: transforms/s and the ratio
+  accuracy      fraction of cubes whose recovered support equals the
+                planted one, checked after the timed region
+  cpu_baseline  the FP64 oracle over the same 1024 cubes on the host cores
+
+--only {copy,lines,batched,plain} runs one part (for profiler runs).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "sparse transforms/sec (batched vs plain) at exact support; line-FFT HBM GB/s"
+WORKLOAD = ("batched: 1024 independent 2-D complex64 cubes, N0,N1 iid from {64,128,256,512}, "
+            "K~U{10..300} on-grid sinusoids, |a|=1, random phase, noiseless, seed 4; "
+            "one persistent launch replayed from a HIP graph")
+KERNEL_SOURCES = ["paper_1711_11407_amd/csrc/kernels.hip", "paper_1711_11407_amd/csrc/device.h",
+                  "paper_1711_11407_amd/csrc/types.h"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+TUNING_FILE = os.path.join(ROOT, "paper_1711_11407_amd", "tuning.json")
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_tuning(kind: str):
+    try:
+        with open(TUNING_FILE) as f:
+            return json.load(f).get("gfx950", {}).get(kind)
+    except FileNotFoundError:
+        return None
+
+
+def traffic_for(kernel: str):
+    """HBM bytes per dispatch from committed rocprofv3 counter summaries, or
+    None when they are absent or the kernels changed since."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except FileNotFoundError:
+        return None
+    if t.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    k = t.get("kernels", {}).get(kernel)
+    if not k:
+        return None
+    return k["hbm_bytes_per_dispatch"]
+
+
+# ---------------------------------------------------------------------------
+# CPU baseline: the FP64 oracle on the host cores
+# ---------------------------------------------------------------------------
+
+def _oracle_worker(idx):
+    os.environ["OMP_NUM_THREADS"] = "1"
+    import oracle as O
+    import workloads as W
+    cubes = W.cfg4(only=idx)
+    t0 = time.perf_counter()
+    for c in cubes:
+        al, ta = O.schedule(c.dims, O.default_max_iters(c.dims), c.schedule_seed)
+        O.run(c.x, al, ta, O.Params(**W.NOISELESS_THRESH, max_k=512))
+    return time.perf_counter() - t0
+
+
+def cpu_baseline(ncubes: int):
+    import multiprocessing as mp
+    cores = min(len(os.sched_getaffinity(0)), 16)
+    chunks = [list(range(i, ncubes, cores)) for i in range(cores)]
+    ctx = mp.get_context("spawn")
+    with ctx.Pool(cores) as pool:
+        times = pool.map(_oracle_worker, chunks)
+    makespan = max(times)
+    cpu = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    cpu = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"value": ncubes / makespan, "unit": "transforms/s", "cores": cores, "kind": "oracle",
+            "sample": f"all {ncubes} cubes of the batched workload, FP64 numpy oracle, one process per "
+                      f"core (OMP_NUM_THREADS=1), cube generation excluded; {cpu}",
+            "cpu_seconds": round(sum(times), 2)}
+
+
+# ---------------------------------------------------------------------------
+# GPU parts
+# ---------------------------------------------------------------------------
+
+def event_time_ms(torch, fn, reps):
+    st = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(st)
+    for _ in range(reps):
+        fn()
+    e1.record(st)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--only", choices=["copy", "lines", "batched", "plain"], default=None)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build measures one GPU only: independent cubes shard across "
+                                   "GPUs with no exchange, and no multi-GPU path is built"}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1711_11407_amd as F
+    import workloads as W
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+
+    if args.only == "copy":
+        # Calibration kernel for the HBM counters: a plain 1 GiB device copy.
+        n = 1 << 27
+        a = torch.ones(n, dtype=torch.complex64, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(args.warmup + args.steps):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        ms = event_time_ms(torch, lambda: b.copy_(a), args.steps)
+        log(f"copy 1 GiB: {ms:.3f} ms, {2 * 8 * n / ms / 1e6:.0f} GB/s")
+        return
+
+    log("generating the batched workload")
+    cubes = W.cfg4()
+    B = len(cubes)
+    specs = [F.CubeSpec(c.dims, seed=c.schedule_seed, max_k=512, **W.NOISELESS_THRESH) for c in cubes]
+    tuning = load_tuning("batched")
+    plan = F.Plan(specs, tuning=tuning)
+    xs = [torch.from_numpy(c.x).to(dev) for c in cubes]
+    bound = plan.bind(xs)
+    outs = bound.outs
+    torch.cuda.synchronize()
+    result = {}
+
+    if args.only in (None, "lines"):
+        sp = torch.empty(plan.spectra_elems(), dtype=torch.complex64, device=dev)
+        for _ in range(max(1, args.warmup)):
+            plan.lines_fft_all(xs, sp)
+        torch.cuda.synchronize()
+        ms = event_time_ms(torch, lambda: plan.lines_fft_all(xs, sp), max(1, args.steps))
+        lines = sum(plan.info[c][1] * (len(specs[c].dims) + 1) for c in range(B))
+        samples = sum(plan.info[c][1] * (len(specs[c].dims) + 1) * plan.info[c][0] for c in range(B))
+        alg = 2 * 8 * samples            # gathered samples read + spectra written
+        gbs = alg / (ms * 1e-3) / 1e9
+        tr = traffic_for("k_lines")
+        result["line_fft"] = {
+            "kernel": "k_lines", "workload": "every cube of the batched workload over its whole budget "
+            "T_max = floor(N/((D+1)L)) (about 100% of the samples)",
+            "lines": int(lines), "samples": int(samples), "ms_per_launch": round(ms, 4),
+            "bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(gbs / HBM_PEAK_GBS, 4), "algorithmic_bytes": int(alg),
+            "traffic": tr}
+        log(f"line FFT: {ms:.3f} ms, {gbs:.0f} GB/s ({100 * gbs / HBM_PEAK_GBS:.1f}% of 8 TB/s)")
+        del sp
+
+    if args.only in (None, "batched"):
+        for _ in range(args.warmup):
+            bound.run_batched()
+        torch.cuda.synchronize()
+        ms = event_time_ms(torch, bound.run_batched, args.steps)
+        value = B / (ms * 1e-3)
+        # Accuracy after the timed region: exact support against the planted truth.
+        infos = torch.stack([o.info for o in outs]).cpu().numpy()
+        exact = 0
+        alg = 0
+        for c in range(B):
+            k, iters, status = (int(v) for v in infos[c, :3])
+            D = len(specs[c].dims)
+            L = plan.info[c][0]
+            alg += iters * (D + 1) * L * 8 + k * (4 * D + 16) + 16
+            if status == 0:
+                got = {tuple(f) for f in outs[c].freqs[:k].cpu().numpy().tolist()}
+                exact += got == {tuple(f) for f in cubes[c].freqs.tolist()}
+        gbs = alg / (ms * 1e-3) / 1e9
+        result.update({
+            "value": round(value, 1), "ms_per_step": round(ms, 4),
+            "roofline": {"kernel": "k_solve_batched", "bound": "hbm", "achieved": round(gbs, 2),
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 5),
+                         "traffic": traffic_for("k_solve_batched"), "algorithmic_bytes": int(alg),
+                         "note": "latency-bound: each cube's iterations are sequential"},
+            "accuracy": {"exact_support_fraction": round(exact / B, 4), "exact_cubes": exact,
+                         "mean_iterations": float(infos[:, 1].mean())},
+        })
+        log(f"batched: {ms:.3f} ms/step, {value:.0f} transforms/s, exact support {exact}/{B}")
+
+    if args.only in (None, "plain"):
+        plain_all = bound.run_plain_all
+        plain_all()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ms = event_time_ms(torch, plain_all, 1)
+        wall = time.perf_counter() - t0
+        pv = B / (ms * 1e-3)
+        result["plain"] = {"value": round(pv, 1), "unit": "transforms/s", "ms_for_batch": round(ms, 3),
+                           "host_wall_ms": round(wall * 1e3, 3)}
+        if "value" in result:
+            result["plain"]["batched_over_plain"] = round(result["value"] / pv, 2)
+        log(f"plain: {ms:.3f} ms for {B} cubes, {pv:.0f} transforms/s")
+
+    if args.only is not None:
+        log(json.dumps(result))
+        return
+
+    line = {
+        "metric": METRIC, "value": result["value"], "unit": "transforms/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": result["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD, "global_batch": B, "parallelism": "single GPU",
+                   "tuning": tuning or "library defaults"},
+        "roofline": result["roofline"], "line_fft": result["line_fft"], "plain": result["plain"],
+        "accuracy": result["accuracy"],
+    }
+    if not args.no_cpu:
+        log("CPU baseline (oracle)")
+        line["cpu_baseline"] = cpu_baseline(B)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

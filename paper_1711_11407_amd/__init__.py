@@ -219,6 +219,11 @@ class Plan:
         B.check(B.lib().fpssft_execute_batched(self._h, ptrs, os_, _stream_ptr(stream)), "execute_batched")
         return outs
 
+    def bind(self, xs, outs: Optional[Sequence[Result]] = None) -> "Bound":
+        """Check the inputs once and keep the marshalled C arguments, so that
+        repeated calls on the same tensors cost one C call each."""
+        return Bound(self, xs, outs)
+
     def lines_fft(self, cube: int, x, t0: int, count: int, out=None, stream=None):
         """Line gather + 1/L-normalised DFT of iterations t0..t0+count-1:
         complex64 [count, D+1, L]."""
@@ -276,6 +281,44 @@ class Plan:
         B.check(B.lib().fpssft_amp_backward_batched(self._h, os_, gp, xp, _stream_ptr(stream)),
                 "amp_backward_batched")
         return grad_xs
+
+
+class Bound:
+    """A plan bound to fixed input and output tensors (see Plan.bind). The
+    caller keeps the tensors alive and unchanged in shape while it is used."""
+
+    def __init__(self, plan: Plan, xs, outs=None):
+        if len(xs) != len(plan):
+            raise ValueError("one input per cube")
+        for c, x in enumerate(xs):
+            plan._check_x(c, x)
+        self.plan = plan
+        self.xs = list(xs)
+        self.outs = list(outs) if outs else [plan.alloc_result(c, xs[c].device) for c in range(len(plan))]
+        self._xp = (C.c_void_p * len(plan))(*[x.data_ptr() for x in self.xs])
+        self._op = (B.Out * len(plan))(*[o.c_out() for o in self.outs])
+        self._x1 = [C.c_void_p(x.data_ptr()) for x in self.xs]
+        self._o1 = [C.byref(self._op[c]) for c in range(len(plan))]
+        self._fn_b = B.lib().fpssft_execute_batched
+        self._fn_p = B.lib().fpssft_execute
+
+    def run_batched(self, stream=None):
+        B.check(self._fn_b(self.plan._h, self._xp, self._op, _stream_ptr(stream)), "execute_batched")
+        return self.outs
+
+    def run_plain(self, cube: int, stream=None):
+        B.check(self._fn_p(self.plan._h, cube, self._x1[cube], self._o1[cube], _stream_ptr(stream)), "execute")
+        return self.outs[cube]
+
+    def run_plain_all(self, stream=None):
+        s = _stream_ptr(stream)
+        h = self.plan._h
+        fn = self._fn_p
+        for c in range(len(self.xs)):
+            st = fn(h, c, self._x1[c], self._o1[c], s)
+            if st < 0:
+                B.check(st, "execute")
+        return self.outs
 
 
 # ---------------------------------------------------------------------------

@@ -151,10 +151,20 @@ __device__ __forceinline__ void stage_generic(const float2* __restrict__ in, flo
 
 __device__ __forceinline__ int ilog2_pow2(int v) { return 31 - __clz(v); }
 
+// Work-group barrier that orders LDS only. Global loads issued before it stay
+// in flight (HIP's __syncthreads also waits for every outstanding global
+// access, which would serialise the register prefetch of the next
+// iteration's samples behind each barrier).
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // Forward, unnormalised FFT of `nl` contiguous lines of length cd.L held in
 // LDS buffer a (b is scratch of the same size). Returns the buffer that holds
 // the result. Must be called by the whole block; ends with a barrier.
-__device__ float2* block_fft(float2* a, float2* b, int nl, const CubeDesc& cd,
+__device__ __forceinline__ float2* block_fft(float2* a, float2* b, int nl, const CubeDesc& cd,
                              const float2* __restrict__ tw) {
   const int L = cd.L;
   const bool pow2 = cd.Lmask >= 0;
@@ -173,7 +183,7 @@ __device__ float2* block_fft(float2* a, float2* b, int nl, const CubeDesc& cd,
       stage_fixed<2>(in, out, nl, L, Ns, lg_nb, lg_ns, pow2, tw);
     else
       stage_generic(in, out, nl, L, Ns, r, tw);
-    __syncthreads();
+    lds_barrier();
     float2* t = in;
     in = out;
     out = t;
@@ -184,7 +194,7 @@ __device__ float2* block_fft(float2* a, float2* b, int nl, const CubeDesc& cd,
 
 // ---------------------------------------------------------------------------
 // Exclusive prefix count of `flag` over the block in thread order (wave64
-// ballots, per-wave counts in LDS `wsum`). Contains two barriers.
+// ballots, per-wave counts in LDS `wsum`). Two barriers.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int block_prefix(bool flag, int* wsum, int* total) {
   const int lane = threadIdx.x & 63;
@@ -193,16 +203,30 @@ __device__ __forceinline__ int block_prefix(bool flag, int* wsum, int* total) {
   const unsigned long long bal = __ballot(flag ? 1 : 0);
   const int before = __popcll(bal & ((1ull << lane) - 1ull));
   if (lane == 0) wsum[wave] = __popcll(bal);
-  __syncthreads();
+  lds_barrier();
   int base = 0, tot = 0;
   for (int w = 0; w < nw; ++w) {
     const int c = wsum[w];
     base += (w < wave) ? c : 0;
     tot += c;
   }
-  __syncthreads();
+  lds_barrier();
   *total = tot;
   return base + before;
+}
+
+// True on every thread iff `flag` is true on some thread. Two barriers.
+__device__ __forceinline__ bool block_any(bool flag, int* wsum) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int nw = (blockDim.x + 63) >> 6;
+  const unsigned long long bal = __ballot(flag ? 1 : 0);
+  if (lane == 0) wsum[wave] = bal != 0ull;
+  lds_barrier();
+  int any = 0;
+  for (int w = 0; w < nw; ++w) any |= wsum[w];
+  lds_barrier();
+  return any != 0;
 }
 
 // ---------------------------------------------------------------------------

@@ -94,11 +94,82 @@ __device__ __forceinline__ SolveLds carve_solve_lds(char* smem, const CubeDesc& 
   return s;
 }
 
-__device__ void solve_cube(const CubeDesc& cd, const float2* __restrict__ x, const OutPtrs out,
-                           const int32_t* __restrict__ sched, const float2* __restrict__ twall,
-                           const float2* __restrict__ pre, int pre_count, char* smem) {
+// Samples (or precomputed spectra) of one iteration held in registers: the
+// D+1 values at l = tid + u * blockDim.x, u < kPfU. Loaded one iteration
+// ahead so that their latency overlaps the current iteration's work.
+constexpr int kPfU = 4;
+
+struct Prefetch {
+  float2 v[kPfU][5];
+};
+
+__device__ __forceinline__ void prefetch_issue(Prefetch& pf, const CubeDesc& cd, const float2* __restrict__ x,
+                                               const int32_t* __restrict__ sched,
+                                               const float2* __restrict__ pre, int pre_count, int t) {
   const int D = cd.D;
   const int L = cd.L;
+  if (t < pre_count) {
+    const float2* src = pre + (int64_t)t * (D + 1) * L;
+#pragma unroll
+    for (int u = 0; u < kPfU; ++u) {
+      const int l = threadIdx.x + u * blockDim.x;
+      if (l < L) {
+#pragma unroll
+        for (int i = 0; i < 5; ++i)
+          if (i <= D) pf.v[u][i] = src[i * L + l];
+      }
+    }
+    return;
+  }
+  const int32_t* row = sched + cd.sched_off + t * 2 * D;
+#pragma unroll
+  for (int u = 0; u < kPfU; ++u) {
+    const int l = threadIdx.x + u * blockDim.x;
+    if (l < L) {
+      uint32_t n[4];
+      int64_t flat = 0;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        if (k < D) {
+          const uint32_t v = (uint32_t)row[k] * (uint32_t)l + (uint32_t)row[D + k];
+          n[k] = umod(v, (uint32_t)cd.dims[k], cd.dmask[k]);
+          flat += (int64_t)n[k] * cd.stride[k];
+        }
+      }
+      pf.v[u][0] = x[flat];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        if (k < D) {
+          const int64_t step = (n[k] + 1 == (uint32_t)cd.dims[k]) ? -(int64_t)(cd.dims[k] - 1) * cd.stride[k]
+                                                                     : cd.stride[k];
+          pf.v[u][k + 1] = x[flat + step];
+        }
+      }
+    }
+  }
+}
+
+__device__ __forceinline__ void prefetch_store(const Prefetch& pf, const CubeDesc& cd, float2* __restrict__ dst,
+                                               float scale) {
+  const int D = cd.D;
+  const int L = cd.L;
+#pragma unroll
+  for (int u = 0; u < kPfU; ++u) {
+    const int l = threadIdx.x + u * blockDim.x;
+    if (l < L) {
+#pragma unroll
+      for (int i = 0; i < 5; ++i)
+        if (i <= D) dst[i * L + l] = c_scale(pf.v[u][i], scale);
+    }
+  }
+}
+
+__device__ __forceinline__ void solve_cube(const CubeDesc& cd, const float2* __restrict__ x, const OutPtrs out,
+                                           const int32_t* __restrict__ sched, const float2* __restrict__ twall,
+                                           const float2* __restrict__ pre, int pre_count, char* smem) {
+  const int D = cd.D;
+  const int L = cd.L;
+  const int T = cd.T;
   const int nl = D + 1;
   const int tid = threadIdx.x;
   const int B = blockDim.x;
@@ -112,23 +183,28 @@ __device__ void solve_cube(const CubeDesc& cd, const float2* __restrict__ x, con
   const float th0 = cd.zero_thresh;
   const float rho = cd.mag_rel_tol;
   const float gtol = cd.grid_tol;
+  const bool use_pf = L <= kPfU * B;
+
+  Prefetch pf;
+  if (use_pf && T > 0) prefetch_issue(pf, cd, x, sched, pre, pre_count, 0);
 
   int kc = 0;
   int status = kStatusIncomplete;
-  int iters = cd.T;
-  for (int t = 0; t < cd.T; ++t) {
+  int iters = T;
+  for (int t = 0; t < T; ++t) {
     const int32_t* at = sched + cd.sched_off + t * 2 * D;
-    float2* S;
-    if (t < pre_count) {
+    const bool precomputed = t < pre_count;
+    if (use_pf) {
+      prefetch_store(pf, cd, s.bufA, precomputed ? 1.0f : cd.inv_L);
+      if (t + 1 < T) prefetch_issue(pf, cd, x, sched, pre, pre_count, t + 1);
+    } else if (precomputed) {
       const float2* src = pre + (int64_t)t * nl * L;
       for (int e = tid; e < nl * L; e += B) s.bufA[e] = src[e];
-      __syncthreads();
-      S = s.bufA;
     } else {
       gather_lines(s.bufA, x, cd, at, 1, cd.inv_L);
-      __syncthreads();
-      S = block_fft(s.bufA, s.bufB, nl, cd, tw);
     }
+    lds_barrier();
+    float2* S = precomputed ? s.bufA : block_fft(s.bufA, s.bufB, nl, cd, tw);
     uint32_t al[4], ta[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
@@ -165,7 +241,7 @@ __device__ void solve_cube(const CubeDesc& cd, const float2* __restrict__ x, con
         }
       }
     }
-    __syncthreads();
+    lds_barrier();
 
     // Test, decode and append, bins in ascending order.
     bool nonzero = false;
@@ -236,7 +312,10 @@ __device__ void solve_cube(const CubeDesc& cd, const float2* __restrict__ x, con
       }
       kc += tot;
     }
-    const int nz = __syncthreads_or(nonzero ? 1 : 0);
+    const bool nz = block_any(nonzero, s.wsum);
+    // Records kept in global memory are read by other threads next
+    // iteration: make the stores visible across the work-group.
+    if (!cd.rec_lds) __syncthreads();
     if (full) {
       status = kStatusCapacity;
       iters = t + 1;
@@ -309,7 +388,7 @@ __global__ void k_zero(float2* const* __restrict__ bufs, const int64_t* __restri
 // The line cotangent goes back through the 1/L DFT (an inverse DFT with 1/L)
 // and is added at the line-0 sample positions.
 // ---------------------------------------------------------------------------
-__device__ void backward_cube(const CubeDesc& cd, const OutPtrs fwd, const float2* __restrict__ ga,
+__device__ __forceinline__ void backward_cube(const CubeDesc& cd, const OutPtrs fwd, const float2* __restrict__ ga,
                               float2* __restrict__ gx, const int32_t* __restrict__ sched,
                               const float2* __restrict__ twall, char* smem) {
   const int D = cd.D;

@@ -375,11 +375,10 @@ fpssft_status build_plan(const fpssft_desc* descs, int32_t batch, const fpssft_t
   // Line-FFT work-group shapes: one G for single-cube calls (largest cube),
   // per-cube G in the all-cubes item list.
   {
-    CubeDesc worst{};
-    worst.D = p->maxD;
-    worst.L = p->maxL;
-    p->lines_G_single = lines_group(worst, tn.lines_wg, p->lds_max);
-    p->lds_lines_single = 2 * (size_t)p->lines_G_single * (p->maxD + 1) * p->maxL * sizeof(float2);
+    // Single-cube calls (the plain path's chunk, spectra export): one
+    // iteration per work-group, for the most parallelism on one cube.
+    p->lines_G_single = 1;
+    p->lds_lines_single = 2 * (size_t)(p->maxD + 1) * p->maxL * sizeof(float2);
     if (p->lds_lines_single > p->lds_max) return FPSSFT_ERR_UNSUPPORTED;
   }
   for (int32_t c = 0; c < batch; ++c) {
