@@ -39,7 +39,6 @@ WORKLOAD = ("batched: 1024 independent 2-D complex64 cubes, N0,N1 iid from {64,1
 KERNEL_SOURCES = ["paper_1711_11407_amd/csrc/kernels.hip", "paper_1711_11407_amd/csrc/device.h",
                   "paper_1711_11407_amd/csrc/types.h"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
-TUNING_FILE = os.path.join(ROOT, "paper_1711_11407_amd", "tuning.json")
 
 
 def log(msg):
@@ -55,11 +54,8 @@ def kernel_source_hash() -> str:
 
 
 def load_tuning(kind: str):
-    try:
-        with open(TUNING_FILE) as f:
-            return json.load(f).get("gfx950", {}).get(kind)
-    except FileNotFoundError:
-        return None
+    from paper_1711_11407_amd import tune
+    return tune.load(tune._arch(), kind)
 
 
 def traffic_for(kernel: str):
@@ -181,11 +177,10 @@ def main():
     result = {}
 
     if args.only in (None, "lines"):
-        sp = torch.empty(plan.spectra_elems(), dtype=torch.complex64, device=dev)
         for _ in range(max(1, args.warmup)):
-            plan.lines_fft_all(xs, sp)
+            bound.run_lines_all()
         torch.cuda.synchronize()
-        ms = event_time_ms(torch, lambda: plan.lines_fft_all(xs, sp), max(1, args.steps))
+        ms = event_time_ms(torch, bound.run_lines_all, max(1, args.steps))
         lines = sum(plan.info[c][1] * (len(specs[c].dims) + 1) for c in range(B))
         samples = sum(plan.info[c][1] * (len(specs[c].dims) + 1) * plan.info[c][0] for c in range(B))
         alg = 2 * 8 * samples            # gathered samples read + spectra written
@@ -199,7 +194,7 @@ def main():
             "frac": round(gbs / HBM_PEAK_GBS, 4), "algorithmic_bytes": int(alg),
             "traffic": tr}
         log(f"line FFT: {ms:.3f} ms, {gbs:.0f} GB/s ({100 * gbs / HBM_PEAK_GBS:.1f}% of 8 TB/s)")
-        del sp
+        bound.spectra = None
 
     if args.only in (None, "batched"):
         for _ in range(args.warmup):

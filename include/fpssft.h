@@ -98,18 +98,22 @@ typedef struct {
   int32_t* info;
 } fpssft_out;
 
-/* Launch-shape choices of the autotuner (0 = library default).
- *  block_threads  threads per work-group of the solve kernels (64..1024,
- *                 multiple of 64)
+/* Launch-shape choices of the autotuner (0 = library default; chunk_iters
+ * is taken as given when >= 0, so pass -1 for its default).
+ *  block_threads  threads per work-group of the solve and adjoint kernels
+ *                 (64..1024, multiple of 64)
  *  max_radix      largest FFT radix used for power-of-two factors (2, 4, 8)
  *  chunk_iters    iterations the plain path gathers and transforms ahead
  *                 in parallel before its sequential decode (>= 0)
- *  lines_wg       lines per work-group of the line gather + FFT kernel */
+ *  lines_wg       consecutive iterations per work item of the persistent
+ *                 line gather + FFT kernel (>= 1)
+ *  lines_threads  threads per work-group of that kernel (64..1024) */
 typedef struct {
   int32_t block_threads;
   int32_t max_radix;
   int32_t chunk_iters;
   int32_t lines_wg;
+  int32_t lines_threads;
 } fpssft_tuning;
 
 typedef struct fpssft_plan_st* fpssft_plan_t;

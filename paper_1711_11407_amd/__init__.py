@@ -137,6 +137,7 @@ class Plan:
             tn.max_radix = int(tuning.get("max_radix", 0))
             tn.chunk_iters = int(tuning.get("chunk_iters", -1))
             tn.lines_wg = int(tuning.get("lines_wg", 0))
+            tn.lines_threads = int(tuning.get("lines_threads", 0))
         h = C.c_void_p()
         B.check(B.lib().fpssft_plan_create(descs, len(self.specs), C.byref(tn) if tn else None, C.byref(h)),
                 "plan_create")
@@ -301,10 +302,22 @@ class Bound:
         self._o1 = [C.byref(self._op[c]) for c in range(len(plan))]
         self._fn_b = B.lib().fpssft_execute_batched
         self._fn_p = B.lib().fpssft_execute
+        self._fn_l = B.lib().fpssft_lines_fft_all
+        self.spectra = None
 
     def run_batched(self, stream=None):
         B.check(self._fn_b(self.plan._h, self._xp, self._op, _stream_ptr(stream)), "execute_batched")
         return self.outs
+
+    def run_lines_all(self, stream=None):
+        """fpssft_lines_fft_all into a packed spectra buffer owned here."""
+        if self.spectra is None:
+            torch = _torch()
+            self.spectra = torch.empty(self.plan.spectra_elems(), dtype=torch.complex64,
+                                       device=self.xs[0].device)
+            self._sp = C.c_void_p(self.spectra.data_ptr())
+        B.check(self._fn_l(self.plan._h, self._xp, self._sp, _stream_ptr(stream)), "lines_fft_all")
+        return self.spectra
 
     def run_plain(self, cube: int, stream=None):
         B.check(self._fn_p(self.plan._h, cube, self._x1[cube], self._o1[cube], _stream_ptr(stream)), "execute")

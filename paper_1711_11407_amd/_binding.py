@@ -46,6 +46,7 @@ class Tuning(C.Structure):
         ("max_radix", C.c_int32),
         ("chunk_iters", C.c_int32),
         ("lines_wg", C.c_int32),
+        ("lines_threads", C.c_int32),
     ]
 
 

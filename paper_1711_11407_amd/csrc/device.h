@@ -7,7 +7,13 @@
 //    butterflies in registers and a generic radix for other prime factors,
 //    twiddles read from one table W_L^k = exp(-j 2 pi k / L) with exact
 //    integer exponents (Eq. hs);
-//  * a block prefix count built from wave64 ballots.
+//  * block prefix count and block "any" built from wave64 ballots, and a
+//    work-group barrier that orders LDS only.
+//
+// Everything is templated on the dimension count D and on whether the line
+// length (hence every N_k, which divides it) is a power of two, so that each
+// kernel instantiation holds only the code it runs: the solve loop is walked
+// once per iteration and must stay small for the instruction cache.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -32,9 +38,71 @@ __device__ __forceinline__ float2 c_mulc(float2 a, float2 b) {
 __device__ __forceinline__ float2 c_scale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
 __device__ __forceinline__ float2 c_conj(float2 a) { return make_float2(a.x, -a.y); }
 
-// x mod n for x < 2^32; `mask` is n - 1 for a power-of-two n, else -1.
-__device__ __forceinline__ uint32_t umod(uint32_t x, uint32_t n, int32_t mask) {
-  return mask >= 0 ? (x & (uint32_t)mask) : (x % n);
+// Global-memory accessors. Pointers read from tables (per-cube inputs and
+// outputs) are generic to the compiler, which then emits flat instructions;
+// those count against the LDS counter too, so every LDS barrier would wait
+// for in-flight global loads. Address-space-1 accesses keep them apart.
+#define FPS_GLOBAL __attribute__((address_space(1)))
+__device__ __forceinline__ float2 ld_g(const float2* p, int64_t i) {
+  return __builtin_bit_cast(float2, ((const FPS_GLOBAL unsigned long long*)p)[i]);
+}
+__device__ __forceinline__ void st_g(float2* p, int64_t i, float2 v) {
+  ((FPS_GLOBAL unsigned long long*)p)[i] = __builtin_bit_cast(unsigned long long, v);
+}
+__device__ __forceinline__ int32_t ld_gi(const int32_t* p, int64_t i) { return ((const FPS_GLOBAL int32_t*)p)[i]; }
+// Elements i and i+1 in one 16-byte load (8-byte aligned).
+typedef float fps_f4a8 __attribute__((ext_vector_type(4), aligned(8)));
+__device__ __forceinline__ void ld_g_pair(const float2* p, int64_t i, float2& u, float2& v) {
+  const fps_f4a8 q = *(const FPS_GLOBAL fps_f4a8*)((const FPS_GLOBAL char*)p + i * 8);
+  u = make_float2(q.x, q.y);
+  v = make_float2(q.z, q.w);
+}
+__device__ __forceinline__ void st_gi(int32_t* p, int64_t i, int32_t v) { ((FPS_GLOBAL int32_t*)p)[i] = v; }
+
+// x mod n for x < 2^32 (n a power of two when kPow2).
+template <bool kPow2>
+__device__ __forceinline__ uint32_t umod(uint32_t x, uint32_t n) {
+  return kPow2 ? (x & (n - 1u)) : (x % n);
+}
+
+__device__ __forceinline__ int ilog2_pow2(uint32_t v) { return 31 - __clz(v); }
+
+// Per-cube geometry, uniform across the work-group (scalar registers).
+template <int D>
+struct Geo {
+  uint32_t L;
+  uint32_t dims[D];
+  uint32_t c[D];  // L / N_k
+  int64_t stride[D];
+};
+
+template <int D>
+__device__ __forceinline__ Geo<D> load_geo(const CubeDesc& cd) {
+  Geo<D> g;
+  g.L = (uint32_t)cd.L;
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    g.dims[k] = (uint32_t)cd.dims[k];
+    g.c[k] = (uint32_t)cd.c[k];
+    g.stride[k] = cd.stride[k];
+  }
+  return g;
+}
+
+// Flat offset of sample l of the line with slope/offset `row` ([2][D]) and
+// the offset steps to the same sample on the shifted lines i = 1..D (the
+// coordinate i-1 advanced by one, wrapping at N_{i-1}).
+template <int D, bool kPow2>
+__device__ __forceinline__ int64_t line_sample(const Geo<D>& g, const int32_t* row, uint32_t l,
+                                               int64_t* step) {
+  int64_t flat = 0;
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    const uint32_t n = umod<kPow2>((uint32_t)row[k] * l + (uint32_t)row[D + k], g.dims[k]);
+    flat += (int64_t)n * g.stride[k];
+    step[k] = (n + 1u == g.dims[k]) ? -(int64_t)(g.dims[k] - 1u) * g.stride[k] : g.stride[k];
+  }
+  return flat;
 }
 
 // ---------------------------------------------------------------------------
@@ -77,21 +145,21 @@ __device__ __forceinline__ void dft8(float2* v) {
 }
 
 // ---------------------------------------------------------------------------
-// One Stockham stage over `nl` lines: in -> out, radix r, Ns = product of
-// the radices of earlier stages. Butterfly j of a line reads in[j + q L/r]
-// (q < r), rotates input q by W_{Ns r}^{q (j mod Ns)}, takes an r-point DFT
-// and writes output p to out[(j - j mod Ns) r + j mod Ns + p Ns].
+// One Stockham stage over `nl` lines: in -> out, radix R, Ns = product of
+// the radices of earlier stages. Butterfly j of a line reads in[j + q L/R]
+// (q < R), rotates input q by W_{Ns R}^{q (j mod Ns)}, takes an R-point DFT
+// and writes output p to out[(j - j mod Ns) R + j mod Ns + p Ns].
 // ---------------------------------------------------------------------------
-template <int R>
-__device__ __forceinline__ void stage_fixed(const float2* __restrict__ in, float2* __restrict__ out,
-                                            int nl, int L, int Ns, int lg_nb, int lg_ns, bool pow2,
-                                            const float2* __restrict__ tw) {
+template <int R, bool kPow2>
+__device__ __forceinline__ void stage_fixed(const float2* __restrict__ in, float2* __restrict__ out, int nl,
+                                            int L, int Ns, const float2* __restrict__ tw) {
   const int nb = L / R;
   const int total = nl * nb;
   const int ts = L / (Ns * R);
+  const int lg_nb = kPow2 ? ilog2_pow2(nb) : 0;
   for (int w = threadIdx.x; w < total; w += blockDim.x) {
     int line, j, k;
-    if (pow2) {
+    if (kPow2) {
       line = w >> lg_nb;
       j = w & (nb - 1);
       k = j & (Ns - 1);
@@ -113,7 +181,7 @@ __device__ __forceinline__ void stage_fixed(const float2* __restrict__ in, float
       dft2(v[0], v[1]);
     } else if (R == 4) {
       dft4(v[0], v[1], v[2], v[3]);
-    } else if (R == 8) {
+    } else {
       dft8(v);
     }
     const int ob = (j - k) * R + k;
@@ -122,11 +190,10 @@ __device__ __forceinline__ void stage_fixed(const float2* __restrict__ in, float
   }
 }
 
-// Any radix r (used for odd prime factors): each butterfly output is an
-// r-term sum read straight from LDS.
-__device__ __forceinline__ void stage_generic(const float2* __restrict__ in, float2* __restrict__ out,
-                                              int nl, int L, int Ns, int r,
-                                              const float2* __restrict__ tw) {
+// Any radix r (odd prime factors): each butterfly output is an r-term sum
+// read straight from LDS.
+__device__ __forceinline__ void stage_generic(const float2* __restrict__ in, float2* __restrict__ out, int nl,
+                                              int L, int Ns, int r, const float2* __restrict__ tw) {
   const int nb = L / r;
   const int total = nl * nb * r;
   const int ts = L / (Ns * r);
@@ -149,8 +216,6 @@ __device__ __forceinline__ void stage_generic(const float2* __restrict__ in, flo
   }
 }
 
-__device__ __forceinline__ int ilog2_pow2(int v) { return 31 - __clz(v); }
-
 // Work-group barrier that orders LDS only. Global loads issued before it stay
 // in flight (HIP's __syncthreads also waits for every outstanding global
 // access, which would serialise the register prefetch of the next
@@ -161,26 +226,24 @@ __device__ __forceinline__ void lds_barrier() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-// Forward, unnormalised FFT of `nl` contiguous lines of length cd.L held in
-// LDS buffer a (b is scratch of the same size). Returns the buffer that holds
-// the result. Must be called by the whole block; ends with a barrier.
-__device__ __forceinline__ float2* block_fft(float2* a, float2* b, int nl, const CubeDesc& cd,
-                             const float2* __restrict__ tw) {
-  const int L = cd.L;
-  const bool pow2 = cd.Lmask >= 0;
+// Forward, unnormalised FFT of `nl` contiguous lines of length L held in LDS
+// buffer a (b is scratch of the same size); radix[] lists the stages (powers
+// of two only when kPow2). Returns the buffer holding the result. Whole
+// work-group; ends with a barrier.
+template <bool kPow2>
+__device__ __forceinline__ float2* block_fft(float2* a, float2* b, int nl, int L, int nstages,
+                                             const int32_t* radix, const float2* __restrict__ tw) {
   float2* in = a;
   float2* out = b;
   int Ns = 1;
-  for (int s = 0; s < cd.nstages; ++s) {
-    const int r = cd.radix[s];
-    const int lg_nb = pow2 ? ilog2_pow2(L / r) : 0;
-    const int lg_ns = pow2 ? ilog2_pow2(Ns) : 0;
+  for (int s = 0; s < nstages; ++s) {
+    const int r = radix[s];
     if (r == 8)
-      stage_fixed<8>(in, out, nl, L, Ns, lg_nb, lg_ns, pow2, tw);
+      stage_fixed<8, kPow2>(in, out, nl, L, Ns, tw);
     else if (r == 4)
-      stage_fixed<4>(in, out, nl, L, Ns, lg_nb, lg_ns, pow2, tw);
-    else if (r == 2)
-      stage_fixed<2>(in, out, nl, L, Ns, lg_nb, lg_ns, pow2, tw);
+      stage_fixed<4, kPow2>(in, out, nl, L, Ns, tw);
+    else if (kPow2 || r == 2)
+      stage_fixed<2, kPow2>(in, out, nl, L, Ns, tw);
     else
       stage_generic(in, out, nl, L, Ns, r, tw);
     lds_barrier();
@@ -230,53 +293,59 @@ __device__ __forceinline__ bool block_any(bool flag, int* wsum) {
 }
 
 // ---------------------------------------------------------------------------
-// Line gather (Eq. sample_slice): the D+1 lines of `nt` consecutive
-// iterations, sample l of line i of iteration tt written (times `scale`) to
-// dst[(tt (D+1) + i) L + l]. Line 0 starts at tau, line i >= 1 at tau with
-// coordinate i-1 advanced by one (mod N_{i-1}). at: the schedule rows
-// [nt][2][D] (slope then offset per iteration).
+// The D+1 samples of line position l (Eq. sample_slice): line 0 at `flat`,
+// line i at flat + step[i-1]. Line D is the shift along the contiguous last
+// dimension, so unless that coordinate wraps its sample is the next element:
+// both come from one 16-byte load.
 // ---------------------------------------------------------------------------
+template <int D>
+__device__ __forceinline__ void load_line_samples(const float2* __restrict__ x, int64_t flat,
+                                                  const int64_t* step, float2* s) {
+  if (step[D - 1] == 1) {
+    ld_g_pair(x, flat, s[0], s[D]);
+  } else {
+    s[0] = ld_g(x, flat);
+    s[D] = ld_g(x, flat + step[D - 1]);
+  }
+#pragma unroll
+  for (int k = 0; k < D - 1; ++k) s[k + 1] = ld_g(x, flat + step[k]);
+}
+
+// ---------------------------------------------------------------------------
+// Line gather: the D+1 lines of `nt` consecutive iterations, sample l of
+// line i of iteration tt written (times `scale`) to dst[(tt (D+1) + i) L + l].
+// at: the schedule rows [nt][2][D]. Each thread issues the loads of kU
+// positions before storing any, to keep more gathers in flight.
+// ---------------------------------------------------------------------------
+template <int D, bool kPow2>
 __device__ __forceinline__ void gather_lines(float2* __restrict__ dst, const float2* __restrict__ x,
-                                             const CubeDesc& cd, const int32_t* __restrict__ at,
-                                             int nt, float scale) {
-  const int D = cd.D;
-  const int L = cd.L;
-  const int total = nt * L;
-  for (int e = threadIdx.x; e < total; e += blockDim.x) {
-    int tt, l;
-    if (cd.Lmask >= 0) {
-      tt = e >> ilog2_pow2(L);
-      l = e & cd.Lmask;
-    } else {
-      tt = e / L;
-      l = e - tt * L;
-    }
-    const int32_t* row = at + tt * 2 * D;
-    uint32_t n[4];
-    int64_t flat = 0;
+                                             const Geo<D>& g, const int32_t* __restrict__ at, int nt,
+                                             float scale) {
+  constexpr int kU = 4;
+  const uint32_t L = g.L;
+  const int total = nt * (int)L;
+  const int B = blockDim.x;
+  for (int e0 = threadIdx.x; e0 < total; e0 += kU * B) {
+    float2 s[kU][D + 1];
+    uint32_t tt[kU], l[kU];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      if (k < D) {
-        const uint32_t v = (uint32_t)row[k] * (uint32_t)l + (uint32_t)row[D + k];
-        n[k] = umod(v, (uint32_t)cd.dims[k], cd.dmask[k]);
-        flat += (int64_t)n[k] * cd.stride[k];
+    for (int u = 0; u < kU; ++u) {
+      const int e = e0 + u * B;
+      tt[u] = kPow2 ? ((uint32_t)e >> ilog2_pow2(L)) : (uint32_t)e / L;
+      l[u] = (uint32_t)e - tt[u] * L;
+      if (e < total) {
+        int64_t step[D];
+        const int64_t flat = line_sample<D, kPow2>(g, at + tt[u] * 2 * D, l[u], step);
+        load_line_samples<D>(x, flat, step, s[u]);
       }
     }
-    float2 s[5];
-    s[0] = x[flat];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      if (k < D) {
-        const int64_t step = (n[k] + 1 == (uint32_t)cd.dims[k])
-                                 ? -(int64_t)(cd.dims[k] - 1) * cd.stride[k]
-                                 : cd.stride[k];
-        s[k + 1] = x[flat + step];
+    for (int u = 0; u < kU; ++u) {
+      if (e0 + u * B < total) {
+        float2* base = dst + (int64_t)tt[u] * (D + 1) * L + l[u];
+#pragma unroll
+        for (int i = 0; i <= D; ++i) base[i * L] = c_scale(s[u][i], scale);
       }
-    }
-    float2* base = dst + (int64_t)tt * (D + 1) * L + l;
-#pragma unroll
-    for (int i = 0; i < 5; ++i) {
-      if (i <= D) base[i * L] = c_scale(s[i], scale);
     }
   }
 }

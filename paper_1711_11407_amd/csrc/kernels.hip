@@ -15,6 +15,9 @@
 //  k_backward       adjoint of the amplitudes with the decisions fixed.
 //  k_reset, k_zero  counter reset and zero fill (kernels, so that they can
 //                   sit inside a captured graph).
+//
+// Kernels are instantiated per (D, power-of-two L, records in LDS); the host
+// picks the instantiation per cube group.
 #include <hip/hip_runtime.h>
 
 #include "device.h"
@@ -24,49 +27,126 @@ namespace fpssft {
 
 static constexpr float kInv2Pi = (float)(1.0 / (2.0 * 3.14159265358979323846));
 
-// ---------------------------------------------------------------------------
-// Line gather + FFT
-// ---------------------------------------------------------------------------
-__global__ void k_lines(const CubeDesc* __restrict__ descs, const LineItem* __restrict__ items,
-                        int nitems, int per_xcd, int single_cube, int t0, int count, int G,
-                        const float2* __restrict__ x_single, const float2* const* __restrict__ xs,
-                        const int32_t* __restrict__ sched, const float2* __restrict__ tw,
-                        float2* __restrict__ out) {
-  extern __shared__ float2 lds_lines[];
-  int cube, tb, tc;
-  int64_t ooff;
-  const float2* x;
-  if (items) {
-    // XCD-aware order: work-groups are dispatched round-robin over the 8
-    // XCDs, so consecutive items (the same cube) go to one XCD and share its
-    // L2.
-    const int b = blockIdx.x;
-    const int it = (b & 7) * per_xcd + (b >> 3);
-    if (it >= nitems) return;
-    const LineItem li = items[it];
-    cube = li.cube;
-    tb = li.t0;
-    tc = li.count;
-    ooff = li.out_off;
-    x = xs[cube];
-  } else {
-    cube = single_cube;
-    tb = t0 + blockIdx.x * G;
-    tc = min(G, t0 + count - tb);
-    if (tc <= 0) return;
-    x = x_single;
-    ooff = (int64_t)(tb - t0) * (descs[cube].D + 1) * descs[cube].L;
+// Samples (or precomputed spectra) of one iteration held in registers: the
+// D+1 values at l = tid + u * blockDim.x, u < kPfU. Loaded one iteration
+// ahead so that their latency overlaps the current iteration's work.
+constexpr int kPfU = 4;
+
+template <int D>
+struct Prefetch {
+  float2 v[kPfU][D + 1];
+};
+
+template <int D, bool kPow2>
+__device__ __forceinline__ void prefetch_issue(Prefetch<D>& pf, const Geo<D>& g, const float2* __restrict__ x,
+                                               const int32_t* __restrict__ row, const float2* __restrict__ pre,
+                                               bool precomputed) {
+  const uint32_t L = g.L;
+#pragma unroll
+  for (int u = 0; u < kPfU; ++u) {
+    const uint32_t l = threadIdx.x + u * blockDim.x;
+    if (l < L) {
+      if (precomputed) {
+#pragma unroll
+        for (int i = 0; i <= D; ++i) pf.v[u][i] = ld_g(pre, i * L + l);
+      } else {
+        int64_t step[D];
+        const int64_t flat = line_sample<D, kPow2>(g, row, l, step);
+        load_line_samples<D>(x, flat, step, pf.v[u]);
+      }
+    }
   }
-  const CubeDesc& cd = descs[cube];
-  const int nl = tc * (cd.D + 1);
-  float2* a = lds_lines;
-  float2* b2 = a + nl * cd.L;
-  gather_lines(a, x, cd, sched + cd.sched_off + tb * 2 * cd.D, tc, cd.inv_L);
+}
+
+template <int D>
+__device__ __forceinline__ void prefetch_store(const Prefetch<D>& pf, uint32_t L, float2* __restrict__ dst,
+                                               float scale) {
+#pragma unroll
+  for (int u = 0; u < kPfU; ++u) {
+    const uint32_t l = threadIdx.x + u * blockDim.x;
+    if (l < L) {
+#pragma unroll
+      for (int i = 0; i <= D; ++i) dst[i * L + l] = c_scale(pf.v[u][i], scale);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Line gather + FFT. Work items are runs of consecutive iterations of one
+// cube. Work-groups are persistent: each takes items from the queue of its
+// XCD (work-groups are dispatched round-robin over the 8 XCDs, and each XCD
+// owns a contiguous, cube-ordered slice of the items, so a cube's lines are
+// gathered through one L2). Within an item the next iteration's samples are
+// loaded into registers while the current one is transformed and written.
+// Single-cube calls (`items` == null) run one iteration per work-group.
+// ---------------------------------------------------------------------------
+template <int D, bool kPow2>
+__device__ __forceinline__ void lines_item(const CubeDesc& cd, const float2* __restrict__ x,
+                                           const int32_t* __restrict__ sched, const float2* __restrict__ twall,
+                                           int tb, int tc, float2* __restrict__ out, float2* bufA, float2* bufB,
+                                           float2* tw, int* tw_cached) {
+  const Geo<D> g = load_geo<D>(cd);
+  const uint32_t L = g.L;
+  const int B = blockDim.x;
+  if (*tw_cached != cd.tw_off) {  // uniform
+    lds_barrier();
+    for (uint32_t e = threadIdx.x; e < L; e += B) tw[e] = ld_g(twall, cd.tw_off + e);
+    *tw_cached = cd.tw_off;
+  }
+  const int32_t* sch = sched + cd.sched_off + tb * 2 * D;
+  const bool use_pf = L <= (uint32_t)(kPfU * B);
+  Prefetch<D> pf;
+  if (use_pf) prefetch_issue<D, kPow2>(pf, g, x, sch, nullptr, false);
+  for (int i = 0; i < tc; ++i) {
+    if (use_pf) {
+      prefetch_store<D>(pf, L, bufA, cd.inv_L);
+      if (i + 1 < tc) prefetch_issue<D, kPow2>(pf, g, x, sch + (i + 1) * 2 * D, nullptr, false);
+    } else {
+      gather_lines<D, kPow2>(bufA, x, g, sch + i * 2 * D, 1, cd.inv_L);
+    }
+    lds_barrier();
+    const float2* S = block_fft<kPow2>(bufA, bufB, D + 1, (int)L, cd.nstages, cd.radix, tw);
+    float2* o = out + (int64_t)i * (D + 1) * L;
+    for (uint32_t e = threadIdx.x; e < (D + 1) * L; e += B) st_g(o, e, S[e]);
+    lds_barrier();
+  }
+}
+
+template <int D, bool kPow2>
+__global__ void k_lines(const CubeDesc* __restrict__ descs, const LineItem* __restrict__ items,
+                        const int32_t* __restrict__ ranges, int* __restrict__ queues, int single_cube, int t0,
+                        int count, const float2* __restrict__ x_single, const float2* const* __restrict__ xs,
+                        const int32_t* __restrict__ sched, const float2* __restrict__ tw,
+                        float2* __restrict__ out, int maxL) {
+  extern __shared__ float2 lds_lines[];
+  __shared__ int s_item;
+  __shared__ int s_tw;
+  float2* bufA = lds_lines;
+  float2* bufB = bufA + (D + 1) * maxL;
+  float2* twl = bufB + (D + 1) * maxL;
+  if (threadIdx.x == 0) s_tw = -1;
   __syncthreads();
-  float2* S = block_fft(a, b2, nl, cd, tw + cd.tw_off);
-  float2* o = out + ooff;
-  const int n = nl * cd.L;
-  for (int e = threadIdx.x; e < n; e += blockDim.x) o[e] = S[e];
+  if (!items) {
+    const int t = t0 + blockIdx.x;
+    if (t >= t0 + count) return;
+    const CubeDesc& cd = descs[single_cube];
+    lines_item<D, kPow2>(cd, x_single, sched, tw, t, 1, out + (int64_t)(t - t0) * (D + 1) * cd.L, bufA, bufB, twl,
+                         &s_tw);
+    return;
+  }
+  const int xcd = blockIdx.x & 7;
+  const int lo = ranges[2 * xcd];
+  const int hi = ranges[2 * xcd + 1];
+  for (;;) {
+    if (threadIdx.x == 0) s_item = lo + atomicAdd(&queues[xcd], 1);
+    __syncthreads();
+    const int it = __builtin_amdgcn_readfirstlane(s_item);
+    __syncthreads();
+    if (it >= hi) break;
+    const LineItem li = items[it];
+    const int c = __builtin_amdgcn_readfirstlane(li.cube);
+    lines_item<D, kPow2>(descs[c], xs[c], sched, tw, li.t0, li.count, out + li.out_off, bufA, bufB, twl, &s_tw);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -75,170 +155,99 @@ __global__ void k_lines(const CubeDesc* __restrict__ descs, const LineItem* __re
 struct SolveLds {
   float2* bufA;
   float2* bufB;
-  int32_t* rec_f;  // [rec_lds][D] frequency indices
+  float2* tw;      // [L] twiddles W_L^k
   float2* rec_a;   // [rec_lds] amplitudes
+  int32_t* rec_f;  // [rec_lds][D] frequency indices
   int* wsum;       // [16]
 };
 
-__device__ __forceinline__ SolveLds carve_solve_lds(char* smem, const CubeDesc& cd) {
+template <int D>
+__device__ __forceinline__ SolveLds carve_solve_lds(char* smem, int L, int rec_lds) {
   SolveLds s;
-  const int nl = cd.D + 1;
   s.bufA = (float2*)smem;
-  s.bufB = s.bufA + nl * cd.L;
-  char* p = (char*)(s.bufB + nl * cd.L);
-  s.rec_a = (float2*)p;
-  p += (size_t)cd.rec_lds * sizeof(float2);
-  s.rec_f = (int32_t*)p;
-  p += (size_t)cd.rec_lds * cd.D * sizeof(int32_t);
-  s.wsum = (int*)p;
+  s.bufB = s.bufA + (D + 1) * L;
+  s.tw = s.bufB + (D + 1) * L;
+  s.rec_a = s.tw + L;
+  s.rec_f = (int32_t*)(s.rec_a + rec_lds);
+  s.wsum = s.rec_f + rec_lds * D;
   return s;
 }
 
-// Samples (or precomputed spectra) of one iteration held in registers: the
-// D+1 values at l = tid + u * blockDim.x, u < kPfU. Loaded one iteration
-// ahead so that their latency overlaps the current iteration's work.
-constexpr int kPfU = 4;
-
-struct Prefetch {
-  float2 v[kPfU][5];
-};
-
-__device__ __forceinline__ void prefetch_issue(Prefetch& pf, const CubeDesc& cd, const float2* __restrict__ x,
-                                               const int32_t* __restrict__ sched,
-                                               const float2* __restrict__ pre, int pre_count, int t) {
-  const int D = cd.D;
-  const int L = cd.L;
-  if (t < pre_count) {
-    const float2* src = pre + (int64_t)t * (D + 1) * L;
-#pragma unroll
-    for (int u = 0; u < kPfU; ++u) {
-      const int l = threadIdx.x + u * blockDim.x;
-      if (l < L) {
-#pragma unroll
-        for (int i = 0; i < 5; ++i)
-          if (i <= D) pf.v[u][i] = src[i * L + l];
-      }
-    }
-    return;
-  }
-  const int32_t* row = sched + cd.sched_off + t * 2 * D;
-#pragma unroll
-  for (int u = 0; u < kPfU; ++u) {
-    const int l = threadIdx.x + u * blockDim.x;
-    if (l < L) {
-      uint32_t n[4];
-      int64_t flat = 0;
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        if (k < D) {
-          const uint32_t v = (uint32_t)row[k] * (uint32_t)l + (uint32_t)row[D + k];
-          n[k] = umod(v, (uint32_t)cd.dims[k], cd.dmask[k]);
-          flat += (int64_t)n[k] * cd.stride[k];
-        }
-      }
-      pf.v[u][0] = x[flat];
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        if (k < D) {
-          const int64_t step = (n[k] + 1 == (uint32_t)cd.dims[k]) ? -(int64_t)(cd.dims[k] - 1) * cd.stride[k]
-                                                                     : cd.stride[k];
-          pf.v[u][k + 1] = x[flat + step];
-        }
-      }
-    }
-  }
-}
-
-__device__ __forceinline__ void prefetch_store(const Prefetch& pf, const CubeDesc& cd, float2* __restrict__ dst,
-                                               float scale) {
-  const int D = cd.D;
-  const int L = cd.L;
-#pragma unroll
-  for (int u = 0; u < kPfU; ++u) {
-    const int l = threadIdx.x + u * blockDim.x;
-    if (l < L) {
-#pragma unroll
-      for (int i = 0; i < 5; ++i)
-        if (i <= D) dst[i * L + l] = c_scale(pf.v[u][i], scale);
-    }
-  }
-}
-
+// kRecLds: the record list lives in LDS and is mirrored to the outputs;
+// otherwise it is read back from the output arrays.
+template <int D, bool kPow2, bool kRecLds>
 __device__ __forceinline__ void solve_cube(const CubeDesc& cd, const float2* __restrict__ x, const OutPtrs out,
                                            const int32_t* __restrict__ sched, const float2* __restrict__ twall,
                                            const float2* __restrict__ pre, int pre_count, char* smem) {
-  const int D = cd.D;
-  const int L = cd.L;
+  const Geo<D> g = load_geo<D>(cd);
+  const uint32_t L = g.L;
   const int T = cd.T;
-  const int nl = D + 1;
+  const int max_k = cd.max_k;
   const int tid = threadIdx.x;
   const int B = blockDim.x;
-  const float2* __restrict__ tw = twall + cd.tw_off;
-  SolveLds s = carve_solve_lds(smem, cd);
-  // Records: LDS copies when they fit, else the output arrays themselves.
-  int32_t* rf = cd.rec_lds ? s.rec_f : out.freqs;
-  float2* ra = cd.rec_lds ? s.rec_a : (float2*)out.amps;
-  float2* oamps = (float2*)out.amps;
-
   const float th0 = cd.zero_thresh;
   const float rho = cd.mag_rel_tol;
   const float gtol = cd.grid_tol;
-  const bool use_pf = L <= kPfU * B;
+  const float inv_L = cd.inv_L;
+  const int32_t* sch = sched + cd.sched_off;
+  SolveLds s = carve_solve_lds<D>(smem, (int)L, kRecLds ? cd.rec_lds : 0);
+  for (uint32_t e = tid; e < L; e += B) s.tw[e] = ld_g(twall, cd.tw_off + e);
+  const float2* tw = s.tw;
+  float2* oamps = (float2*)out.amps;
+  const bool use_pf = L <= (uint32_t)(kPfU * B);
 
-  Prefetch pf;
-  if (use_pf && T > 0) prefetch_issue(pf, cd, x, sched, pre, pre_count, 0);
+  Prefetch<D> pf;
+  if (use_pf) prefetch_issue<D, kPow2>(pf, g, x, sch, pre, 0 < pre_count);
 
   int kc = 0;
   int status = kStatusIncomplete;
   int iters = T;
   for (int t = 0; t < T; ++t) {
-    const int32_t* at = sched + cd.sched_off + t * 2 * D;
+    const int32_t* at = sch + t * 2 * D;
     const bool precomputed = t < pre_count;
     if (use_pf) {
-      prefetch_store(pf, cd, s.bufA, precomputed ? 1.0f : cd.inv_L);
-      if (t + 1 < T) prefetch_issue(pf, cd, x, sched, pre, pre_count, t + 1);
+      prefetch_store<D>(pf, L, s.bufA, precomputed ? 1.0f : inv_L);
+      if (t + 1 < T)
+        prefetch_issue<D, kPow2>(pf, g, x, at + 2 * D, pre + (int64_t)(t + 1) * (D + 1) * L, t + 1 < pre_count);
     } else if (precomputed) {
-      const float2* src = pre + (int64_t)t * nl * L;
-      for (int e = tid; e < nl * L; e += B) s.bufA[e] = src[e];
+      const float2* src = pre + (int64_t)t * (D + 1) * L;
+      for (uint32_t e = tid; e < (D + 1) * L; e += B) s.bufA[e] = ld_g(src, e);
     } else {
-      gather_lines(s.bufA, x, cd, at, 1, cd.inv_L);
+      gather_lines<D, kPow2>(s.bufA, x, g, at, 1, inv_L);
     }
     lds_barrier();
-    float2* S = precomputed ? s.bufA : block_fft(s.bufA, s.bufB, nl, cd, tw);
-    uint32_t al[4], ta[4];
+    float2* S = precomputed ? s.bufA : block_fft<kPow2>(s.bufA, s.bufB, D + 1, (int)L, cd.nstages, cd.radix, tw);
+    uint32_t al[D], ta[D];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      al[k] = k < D ? (uint32_t)at[k] : 0u;
-      ta[k] = k < D ? (uint32_t)at[D + k] : 0u;
+    for (int k = 0; k < D; ++k) {
+      al[k] = (uint32_t)at[k];
+      ta[k] = (uint32_t)at[D + k];
     }
 
     // Peel: subtract every earlier record's projection a e^{+j 2 pi p / L}
     // from bin b of each line, b = [sum_k alpha_k c_k m_k]_L and
     // p = [sum_k tau_k^{(i)} c_k m_k]_L (Eq. freqSum, Eq. orthogonality).
     for (int j = tid; j < kc; j += B) {
-      uint32_t g[4];
+      uint32_t gk[D];
       uint32_t b = 0, p0 = 0;
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        if (k < D) {
-          g[k] = (uint32_t)cd.c[k] * (uint32_t)rf[j * D + k];
-          b = umod(b + al[k] * g[k], L, cd.Lmask);
-          p0 = umod(p0 + ta[k] * g[k], L, cd.Lmask);
-        }
+      for (int k = 0; k < D; ++k) {
+        const int32_t f = kRecLds ? s.rec_f[j * D + k] : ld_gi(out.freqs, j * D + k);
+        gk[k] = g.c[k] * (uint32_t)f;
+        b = umod<kPow2>(b + al[k] * gk[k], L);
+        p0 = umod<kPow2>(p0 + ta[k] * gk[k], L);
       }
-      const float2 a = ra[j];
+      const float2 a = kRecLds ? s.rec_a[j] : ld_g(oamps, j);
       float2 c = c_mulc(a, tw[p0]);
       atomicAdd(&S[b].x, -c.x);
       atomicAdd(&S[b].y, -c.y);
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        if (k < D) {
-          uint32_t p = p0 + g[k];
-          if (p >= (uint32_t)L) p -= L;
-          c = c_mulc(a, tw[p]);
-          atomicAdd(&S[(k + 1) * L + b].x, -c.x);
-          atomicAdd(&S[(k + 1) * L + b].y, -c.y);
-        }
+      for (int k = 0; k < D; ++k) {
+        uint32_t p = p0 + gk[k];
+        if (p >= L) p -= L;
+        c = c_mulc(a, tw[p]);
+        atomicAdd(&S[(k + 1) * L + b].x, -c.x);
+        atomicAdd(&S[(k + 1) * L + b].y, -c.y);
       }
     }
     lds_barrier();
@@ -246,10 +255,10 @@ __device__ __forceinline__ void solve_cube(const CubeDesc& cd, const float2* __r
     // Test, decode and append, bins in ascending order.
     bool nonzero = false;
     bool full = false;
-    for (int m0 = 0; m0 < L; m0 += B) {
-      const int m = m0 + tid;
+    for (uint32_t m0 = 0; m0 < L; m0 += B) {
+      const uint32_t m = m0 + tid;
       bool cand = false;
-      int f[4] = {0, 0, 0, 0};
+      int f[D];
       float2 amp = make_float2(0.f, 0.f);
       if (m < L) {
         const float2 r0 = S[m];
@@ -257,33 +266,29 @@ __device__ __forceinline__ void solve_cube(const CubeDesc& cd, const float2* __r
         nonzero |= mag0 > th0;
         cand = mag0 > th0;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          if (k < D) {
-            const float2 ri = S[(k + 1) * L + m];
-            const float mi = sqrtf(ri.x * ri.x + ri.y * ri.y);
-            nonzero |= mi > th0;
-            cand = cand && (fabsf(mi - mag0) <= rho * mag0);
-            const float2 z = c_mulc(ri, r0);
-            const float phi = atan2f(z.y, z.x);
-            const float u = ((float)cd.dims[k] * phi) * kInv2Pi;
-            const float v = rintf(u);
-            if (gtol >= 0.f) cand = cand && (fabsf(u - v) <= gtol);
-            int fi = (int)v % cd.dims[k];
-            if (fi < 0) fi += cd.dims[k];
-            f[k] = fi;
-          }
+        for (int k = 0; k < D; ++k) {
+          const float2 ri = S[(k + 1) * L + m];
+          const float mi = sqrtf(ri.x * ri.x + ri.y * ri.y);
+          nonzero |= mi > th0;
+          cand = cand && (fabsf(mi - mag0) <= rho * mag0);
+          const float2 z = c_mulc(ri, r0);
+          const float phi = atan2f(z.y, z.x);
+          const float u = ((float)g.dims[k] * phi) * kInv2Pi;
+          const float v = rintf(u);
+          if (gtol >= 0.f) cand = cand && (fabsf(u - v) <= gtol);
+          int fi = (int)v % (int)g.dims[k];
+          if (fi < 0) fi += (int)g.dims[k];
+          f[k] = fi;
         }
         if (cand) {
           uint32_t b = 0, q = 0;
 #pragma unroll
-          for (int k = 0; k < 4; ++k) {
-            if (k < D) {
-              const uint32_t g = (uint32_t)cd.c[k] * (uint32_t)f[k];
-              b = umod(b + al[k] * g, L, cd.Lmask);
-              q = umod(q + ta[k] * g, L, cd.Lmask);
-            }
+          for (int k = 0; k < D; ++k) {
+            const uint32_t gk = g.c[k] * (uint32_t)f[k];
+            b = umod<kPow2>(b + al[k] * gk, L);
+            q = umod<kPow2>(q + ta[k] * gk, L);
           }
-          cand = (b == (uint32_t)m);
+          cand = (b == m);
           amp = c_mul(r0, tw[q]);  // r0 exp(-j 2 pi q / L)
         }
       }
@@ -291,23 +296,21 @@ __device__ __forceinline__ void solve_cube(const CubeDesc& cd, const float2* __r
       const int pos = block_prefix(cand, s.wsum, &tot);
       if (cand) {
         const int idx = kc + pos;
-        if (idx < cd.max_k) {
+        if (idx < max_k) {
 #pragma unroll
-          for (int k = 0; k < 4; ++k) {
-            if (k < D) {
-              rf[idx * D + k] = f[k];
-              if (cd.rec_lds) out.freqs[idx * D + k] = f[k];
-            }
+          for (int k = 0; k < D; ++k) {
+            if (kRecLds) s.rec_f[idx * D + k] = f[k];
+            st_gi(out.freqs, idx * D + k, f[k]);
           }
-          ra[idx] = amp;
-          if (cd.rec_lds) oamps[idx] = amp;
-          out.rec_iter[idx] = t;
-          out.rec_bin[idx] = m;
+          if (kRecLds) s.rec_a[idx] = amp;
+          st_g(oamps, idx, amp);
+          st_gi(out.rec_iter, idx, t);
+          st_gi(out.rec_bin, idx, (int32_t)m);
         }
       }
-      if (kc + tot > cd.max_k) {
+      if (kc + tot > max_k) {
         full = true;
-        kc = cd.max_k;
+        kc = max_k;
         break;
       }
       kc += tot;
@@ -315,7 +318,7 @@ __device__ __forceinline__ void solve_cube(const CubeDesc& cd, const float2* __r
     const bool nz = block_any(nonzero, s.wsum);
     // Records kept in global memory are read by other threads next
     // iteration: make the stores visible across the work-group.
-    if (!cd.rec_lds) __syncthreads();
+    if (!kRecLds) __syncthreads();
     if (full) {
       status = kStatusCapacity;
       iters = t + 1;
@@ -328,39 +331,41 @@ __device__ __forceinline__ void solve_cube(const CubeDesc& cd, const float2* __r
     }
   }
   if (tid == 0) {
-    out.info[0] = kc;
-    out.info[1] = iters;
-    out.info[2] = status;
-    out.info[3] = 0;
+    st_gi(out.info, 0, kc);
+    st_gi(out.info, 1, iters);
+    st_gi(out.info, 2, status);
+    st_gi(out.info, 3, 0);
   }
   __syncthreads();
 }
 
+template <int D, bool kPow2, bool kRecLds>
 __global__ void k_solve_plain(const CubeDesc* __restrict__ descs, int cube, const float2* __restrict__ x,
-                              OutPtrs out, const int32_t* __restrict__ sched,
-                              const float2* __restrict__ tw, const float2* __restrict__ pre,
-                              int pre_count) {
+                              OutPtrs out, const int32_t* __restrict__ sched, const float2* __restrict__ tw,
+                              const float2* __restrict__ pre, int pre_count) {
   extern __shared__ char lds_solve[];
-  solve_cube(descs[cube], x, out, sched, tw, pre, pre_count, lds_solve);
+  solve_cube<D, kPow2, kRecLds>(descs[cube], x, out, sched, tw, pre, pre_count, lds_solve);
 }
 
 // Persistent: every work-group loops taking the next cube of `order` from
 // the queue counter; it leaves when the counter passes the cube count, so
 // every wave reaches the exit.
+template <int D, bool kPow2, bool kRecLds>
 __global__ void k_solve_batched(const CubeDesc* __restrict__ descs, const float2* const* __restrict__ xs,
                                 const OutPtrs* __restrict__ outs, const int32_t* __restrict__ sched,
-                                const float2* __restrict__ tw, const int32_t* __restrict__ order,
-                                int ncubes, int* __restrict__ queue) {
+                                const float2* __restrict__ tw, const int32_t* __restrict__ order, int ncubes,
+                                int* __restrict__ queue) {
   extern __shared__ char lds_solve[];
   __shared__ int s_idx;
   for (;;) {
     if (threadIdx.x == 0) s_idx = atomicAdd(queue, 1);
     __syncthreads();
-    const int idx = s_idx;
+    // uniform across the work-group: keep it in a scalar register
+    const int idx = __builtin_amdgcn_readfirstlane(s_idx);
     __syncthreads();
     if (idx >= ncubes) break;
-    const int c = order[idx];
-    solve_cube(descs[c], xs[c], outs[c], sched, tw, nullptr, 0, lds_solve);
+    const int c = __builtin_amdgcn_readfirstlane(order[idx]);
+    solve_cube<D, kPow2, kRecLds>(descs[c], xs[c], outs[c], sched, tw, nullptr, 0, lds_solve);
   }
 }
 
@@ -369,13 +374,13 @@ __global__ void k_reset(int* __restrict__ p, int n) {
 }
 
 // Zero fill of one buffer per blockIdx.y (float2 elements).
-__global__ void k_zero(float2* const* __restrict__ bufs, const int64_t* __restrict__ lens,
-                       float2* single, int64_t single_len) {
+__global__ void k_zero(float2* const* __restrict__ bufs, const int64_t* __restrict__ lens, float2* single,
+                       int64_t single_len) {
   float2* p = single ? single : bufs[blockIdx.y];
   const int64_t n = single ? single_len : lens[blockIdx.y];
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
-    p[i] = make_float2(0.f, 0.f);
+    st_g(p, i, make_float2(0.f, 0.f));
 }
 
 // ---------------------------------------------------------------------------
@@ -388,53 +393,54 @@ __global__ void k_zero(float2* const* __restrict__ bufs, const int64_t* __restri
 // The line cotangent goes back through the 1/L DFT (an inverse DFT with 1/L)
 // and is added at the line-0 sample positions.
 // ---------------------------------------------------------------------------
+template <int D, bool kPow2>
 __device__ __forceinline__ void backward_cube(const CubeDesc& cd, const OutPtrs fwd, const float2* __restrict__ ga,
-                              float2* __restrict__ gx, const int32_t* __restrict__ sched,
-                              const float2* __restrict__ twall, char* smem) {
-  const int D = cd.D;
-  const int L = cd.L;
+                                              float2* __restrict__ gx, const int32_t* __restrict__ sched,
+                                              const float2* __restrict__ twall, char* smem) {
+  const Geo<D> g = load_geo<D>(cd);
+  const uint32_t L = g.L;
   const int tid = threadIdx.x;
   const int B = blockDim.x;
-  const float2* __restrict__ tw = twall + cd.tw_off;
-  float2* rbar = (float2*)smem;     // [L] line-0 spectrum cotangent
-  float2* scratch = rbar + L;       // [L] FFT ping-pong
-  float2* abar = scratch + L;       // [max_k]
+  float2* rbar = (float2*)smem;  // [L] line-0 spectrum cotangent
+  float2* scratch = rbar + L;    // [L] FFT ping-pong
+  float2* tw = scratch + L;      // [L] twiddles
+  float2* abar = tw + L;         // [max_k]
   __shared__ int sh_s, sh_t;
 
-  const int k = min(fwd.info[0], cd.max_k);
-  for (int i = tid; i < k; i += B) abar[i] = ga[i];
+  for (uint32_t e = tid; e < L; e += B) tw[e] = ld_g(twall, cd.tw_off + e);
+  const int k = min(ld_gi(fwd.info, 0), cd.max_k);
+  for (int i = tid; i < k; i += B) abar[i] = ld_g(ga, i);
   __syncthreads();
   int e = k;
   while (e > 0) {
     if (tid == 0) {
-      const int tt = fwd.rec_iter[e - 1];
+      const int tt = ld_gi(fwd.rec_iter, e - 1);
       int s0 = e - 1;
-      while (s0 > 0 && fwd.rec_iter[s0 - 1] == tt) --s0;
+      while (s0 > 0 && ld_gi(fwd.rec_iter, s0 - 1) == tt) --s0;
       sh_s = s0;
       sh_t = tt;
     }
-    for (int m = tid; m < L; m += B) rbar[m] = make_float2(0.f, 0.f);
+    for (uint32_t m = tid; m < L; m += B) rbar[m] = make_float2(0.f, 0.f);
     __syncthreads();
     const int s0 = sh_s;
     const int t = sh_t;
-    const int32_t* at = sched + cd.sched_off + ((t >= 0 && t < cd.T) ? t : 0) * 2 * D;
-    uint32_t al[4], ta[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      al[q] = q < D ? (uint32_t)at[q] : 0u;
-      ta[q] = q < D ? (uint32_t)at[D + q] : 0u;
-    }
-    // Records of iteration t: distinct bins, so plain stores. Entries that
-    // no forward run can have written (bin or iteration out of range) are
-    // skipped rather than trusted as LDS or schedule indices.
+    // Entries that no forward run can have written (bin or iteration out of
+    // range) are skipped rather than trusted as LDS or schedule indices.
     const bool t_ok = t >= 0 && t < cd.T;
+    const int32_t* at = sched + cd.sched_off + (t_ok ? t : 0) * 2 * D;
+    uint32_t al[D], ta[D];
+#pragma unroll
+    for (int q = 0; q < D; ++q) {
+      al[q] = (uint32_t)at[q];
+      ta[q] = (uint32_t)at[D + q];
+    }
+    // Records of iteration t: distinct bins, so plain stores.
     for (int i = s0 + tid; i < e; i += B) {
-      const int m = fwd.rec_bin[i];
-      if (!t_ok || m < 0 || m >= L) continue;
+      const int m = ld_gi(fwd.rec_bin, i);
+      if (!t_ok || m < 0 || m >= (int)L) continue;
       uint32_t p = 0;
 #pragma unroll
-      for (int q = 0; q < 4; ++q)
-        if (q < D) p = umod(p + ta[q] * ((uint32_t)cd.c[q] * (uint32_t)fwd.freqs[i * D + q]), L, cd.Lmask);
+      for (int q = 0; q < D; ++q) p = umod<kPow2>(p + ta[q] * (g.c[q] * (uint32_t)ld_gi(fwd.freqs, i * D + q)), L);
       rbar[m] = c_mulc(abar[i], tw[p]);
     }
     __syncthreads();
@@ -442,12 +448,10 @@ __device__ __forceinline__ void backward_cube(const CubeDesc& cd, const OutPtrs 
     for (int j = tid; j < s0; j += B) {
       uint32_t b = 0, p = 0;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        if (q < D) {
-          const uint32_t g = (uint32_t)cd.c[q] * (uint32_t)fwd.freqs[j * D + q];
-          b = umod(b + al[q] * g, L, cd.Lmask);
-          p = umod(p + ta[q] * g, L, cd.Lmask);
-        }
+      for (int q = 0; q < D; ++q) {
+        const uint32_t gq = g.c[q] * (uint32_t)ld_gi(fwd.freqs, j * D + q);
+        b = umod<kPow2>(b + al[q] * gq, L);
+        p = umod<kPow2>(p + ta[q] * gq, L);
       }
       const float2 v = rbar[b];
       abar[j] = c_sub(abar[j], c_mul(tw[p], v));
@@ -455,74 +459,129 @@ __device__ __forceinline__ void backward_cube(const CubeDesc& cd, const OutPtrs 
     __syncthreads();
     // s_bar(l) = (1/L) sum_m r_bar(m) e^{+j 2 pi l m / L}
     //          = (1/L) conj(FFT(conj(r_bar)))(l).
-    for (int m = tid; m < L; m += B) rbar[m] = c_scale(c_conj(rbar[m]), cd.inv_L);
+    for (uint32_t m = tid; m < L; m += B) rbar[m] = c_scale(c_conj(rbar[m]), cd.inv_L);
     __syncthreads();
-    const float2* S = block_fft(rbar, scratch, 1, cd, tw);
-    for (int l = tid; l < L; l += B) {
-      int64_t flat = 0;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        if (q < D) {
-          const uint32_t v = al[q] * (uint32_t)l + ta[q];
-          flat += (int64_t)umod(v, (uint32_t)cd.dims[q], cd.dmask[q]) * cd.stride[q];
-        }
+    const float2* S = block_fft<kPow2>(rbar, scratch, 1, (int)L, cd.nstages, cd.radix, tw);
+    if (t_ok) {
+      for (uint32_t l = tid; l < L; l += B) {
+        int64_t step[D];
+        const int64_t flat = line_sample<D, kPow2>(g, at, l, step);
+        const float2 v = c_conj(S[l]);
+        unsafeAtomicAdd(&gx[flat].x, v.x);
+        unsafeAtomicAdd(&gx[flat].y, v.y);
       }
-      const float2 g = c_conj(S[l]);
-      unsafeAtomicAdd(&gx[flat].x, g.x);
-      unsafeAtomicAdd(&gx[flat].y, g.y);
     }
     __syncthreads();
     e = s0;
   }
 }
 
+template <int D, bool kPow2>
 __global__ void k_backward(const CubeDesc* __restrict__ descs, int cube, OutPtrs fwd_single,
                            const float2* __restrict__ ga_single, float2* __restrict__ gx_single,
-                           const OutPtrs* __restrict__ fwds, const float2* const* __restrict__ gas,
-                           float2* const* __restrict__ gxs, const int32_t* __restrict__ sched,
-                           const float2* __restrict__ tw) {
+                           const int32_t* __restrict__ order, const OutPtrs* __restrict__ fwds,
+                           const float2* const* __restrict__ gas, float2* const* __restrict__ gxs,
+                           const int32_t* __restrict__ sched, const float2* __restrict__ tw) {
   extern __shared__ char lds_bwd[];
   if (cube >= 0) {
-    backward_cube(descs[cube], fwd_single, ga_single, gx_single, sched, tw, lds_bwd);
+    backward_cube<D, kPow2>(descs[cube], fwd_single, ga_single, gx_single, sched, tw, lds_bwd);
   } else {
-    const int c = blockIdx.x;
-    backward_cube(descs[c], fwds[c], gas[c], gxs[c], sched, tw, lds_bwd);
+    const int c = order[blockIdx.x];
+    backward_cube<D, kPow2>(descs[c], fwds[c], gas[c], gxs[c], sched, tw, lds_bwd);
   }
 }
 
 // ---------------------------------------------------------------------------
-// Host-side launchers.
+// Instantiation tables and host-side launchers.
 // ---------------------------------------------------------------------------
-hipError_t launch_lines_single(const LaunchCtx& ctx, int cube, const float2* x, int t0, int count,
-                               int G, float2* out, size_t lds, int threads, hipStream_t st) {
-  const int grid = (count + G - 1) / G;
-  hipLaunchKernelGGL(k_lines, dim3(grid), dim3(threads), lds, st, ctx.descs, (const LineItem*)nullptr, 0,
-                     0, cube, t0, count, G, x, (const float2* const*)nullptr, ctx.sched, ctx.tw, out);
+#define FPS_DISPATCH_D(D_, ...)                 \
+  switch (D_) {                                 \
+    case 1: {                                   \
+      constexpr int kD = 1;                     \
+      __VA_ARGS__;                              \
+      break;                                    \
+    }                                           \
+    case 2: {                                   \
+      constexpr int kD = 2;                     \
+      __VA_ARGS__;                              \
+      break;                                    \
+    }                                           \
+    case 3: {                                   \
+      constexpr int kD = 3;                     \
+      __VA_ARGS__;                              \
+      break;                                    \
+    }                                           \
+    default: {                                  \
+      constexpr int kD = 4;                     \
+      __VA_ARGS__;                              \
+      break;                                    \
+    }                                           \
+  }
+
+#define FPS_DISPATCH_B(flag, name, ...) \
+  if (flag) {                           \
+    constexpr bool name = true;         \
+    __VA_ARGS__;                        \
+  } else {                              \
+    constexpr bool name = false;        \
+    __VA_ARGS__;                        \
+  }
+
+const void* kernel_ptr(KernelKind kind, const KernelKey& key) {
+  const void* fn = nullptr;
+  FPS_DISPATCH_D(key.D, FPS_DISPATCH_B(key.pow2, kP, FPS_DISPATCH_B(key.rec_lds, kR, {
+    switch (kind) {
+      case KernelKind::kLines: fn = (const void*)k_lines<kD, kP>; break;
+      case KernelKind::kSolvePlain: fn = (const void*)k_solve_plain<kD, kP, kR>; break;
+      case KernelKind::kSolveBatched: fn = (const void*)k_solve_batched<kD, kP, kR>; break;
+      case KernelKind::kBackward: fn = (const void*)k_backward<kD, kP>; break;
+    }
+  })))
+  return fn;
+}
+
+hipError_t launch_lines_single(const LaunchCtx& ctx, const KernelKey& key, int cube, const float2* x, int t0,
+                               int count, float2* out, int maxL, size_t lds, int threads, hipStream_t st) {
+  FPS_DISPATCH_D(key.D, FPS_DISPATCH_B(key.pow2, kP, {
+    hipLaunchKernelGGL((k_lines<kD, kP>), dim3(count), dim3(threads), lds, st, ctx.descs,
+                       (const LineItem*)nullptr, (const int32_t*)nullptr, (int*)nullptr, cube, t0, count, x,
+                       (const float2* const*)nullptr, ctx.sched, ctx.tw, out, maxL);
+  }))
   return hipGetLastError();
 }
 
-hipError_t launch_lines_items(const LaunchCtx& ctx, const LineItem* items, int nitems,
-                              const float2* const* xs, float2* out, size_t lds, int threads,
+hipError_t launch_lines_items(const LaunchCtx& ctx, const KernelKey& key, const LineItem* items,
+                              const int32_t* ranges, int* queues, int grid, const float2* const* xs, float2* out,
+                              int maxL, size_t lds, int threads, hipStream_t st) {
+  FPS_DISPATCH_D(key.D, FPS_DISPATCH_B(key.pow2, kP, {
+    hipLaunchKernelGGL((k_lines<kD, kP>), dim3(grid), dim3(threads), lds, st, ctx.descs, items, ranges, queues, 0,
+                       0, 0, (const float2*)nullptr, xs, ctx.sched, ctx.tw, out, maxL);
+  }))
+  return hipGetLastError();
+}
+
+hipError_t launch_solve_plain(const LaunchCtx& ctx, const KernelKey& key, int cube, const float2* x,
+                              const OutPtrs& out, const float2* pre, int pre_count, size_t lds, int threads,
                               hipStream_t st) {
-  const int per_xcd = (nitems + 7) / 8;
-  hipLaunchKernelGGL(k_lines, dim3(per_xcd * 8), dim3(threads), lds, st, ctx.descs, items, nitems,
-                     per_xcd, 0, 0, 0, 0, (const float2*)nullptr, xs, ctx.sched, ctx.tw, out);
+  FPS_DISPATCH_D(key.D, FPS_DISPATCH_B(key.pow2, kP, FPS_DISPATCH_B(key.rec_lds, kR, {
+    hipLaunchKernelGGL((k_solve_plain<kD, kP, kR>), dim3(1), dim3(threads), lds, st, ctx.descs, cube, x, out,
+                       ctx.sched, ctx.tw, pre, pre_count);
+  })))
   return hipGetLastError();
 }
 
-hipError_t launch_solve_plain(const LaunchCtx& ctx, int cube, const float2* x, const OutPtrs& out,
-                              const float2* pre, int pre_count, size_t lds, int threads, hipStream_t st) {
-  hipLaunchKernelGGL(k_solve_plain, dim3(1), dim3(threads), lds, st, ctx.descs, cube, x, out, ctx.sched,
-                     ctx.tw, pre, pre_count);
+hipError_t launch_reset(int* p, int n, hipStream_t st) {
+  hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, st, p, n);
   return hipGetLastError();
 }
 
-hipError_t launch_solve_batched(const LaunchCtx& ctx, const float2* const* xs, const OutPtrs* outs,
-                                const int32_t* order, int ncubes, int* queue, int grid, size_t lds,
-                                int threads, hipStream_t st) {
-  hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, st, queue, 1);
-  hipLaunchKernelGGL(k_solve_batched, dim3(grid), dim3(threads), lds, st, ctx.descs, xs, outs, ctx.sched,
-                     ctx.tw, order, ncubes, queue);
+hipError_t launch_solve_batched(const LaunchCtx& ctx, const KernelKey& key, const float2* const* xs,
+                                const OutPtrs* outs, const int32_t* order, int ncubes, int* queue, int grid,
+                                size_t lds, int threads, hipStream_t st) {
+  FPS_DISPATCH_D(key.D, FPS_DISPATCH_B(key.pow2, kP, FPS_DISPATCH_B(key.rec_lds, kR, {
+    hipLaunchKernelGGL((k_solve_batched<kD, kP, kR>), dim3(grid), dim3(threads), lds, st, ctx.descs, xs, outs,
+                       ctx.sched, ctx.tw, order, ncubes, queue);
+  })))
   return hipGetLastError();
 }
 
@@ -535,36 +594,34 @@ hipError_t launch_zero_single(float2* p, int64_t n, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_zero_multi(float2* const* bufs, const int64_t* lens, int nbufs, int64_t maxlen,
-                             hipStream_t st) {
+hipError_t launch_zero_multi(float2* const* bufs, const int64_t* lens, int nbufs, int64_t maxlen, hipStream_t st) {
   int64_t blocks = (maxlen + 255) / 256;
   if (blocks > 512) blocks = 512;
   if (blocks < 1) blocks = 1;
-  hipLaunchKernelGGL(k_zero, dim3((unsigned)blocks, nbufs), dim3(256), 0, st, bufs, lens,
-                     (float2*)nullptr, (int64_t)0);
+  hipLaunchKernelGGL(k_zero, dim3((unsigned)blocks, nbufs), dim3(256), 0, st, bufs, lens, (float2*)nullptr,
+                     (int64_t)0);
   return hipGetLastError();
 }
 
-hipError_t launch_backward_single(const LaunchCtx& ctx, int cube, const OutPtrs& fwd, const float2* ga,
-                                  float2* gx, size_t lds, int threads, hipStream_t st) {
-  hipLaunchKernelGGL(k_backward, dim3(1), dim3(threads), lds, st, ctx.descs, cube, fwd, ga, gx,
-                     (const OutPtrs*)nullptr, (const float2* const*)nullptr, (float2* const*)nullptr,
-                     ctx.sched, ctx.tw);
+hipError_t launch_backward_single(const LaunchCtx& ctx, const KernelKey& key, int cube, const OutPtrs& fwd,
+                                  const float2* ga, float2* gx, size_t lds, int threads, hipStream_t st) {
+  FPS_DISPATCH_D(key.D, FPS_DISPATCH_B(key.pow2, kP, {
+    hipLaunchKernelGGL((k_backward<kD, kP>), dim3(1), dim3(threads), lds, st, ctx.descs, cube, fwd, ga, gx,
+                       (const int32_t*)nullptr, (const OutPtrs*)nullptr, (const float2* const*)nullptr,
+                       (float2* const*)nullptr, ctx.sched, ctx.tw);
+  }))
   return hipGetLastError();
 }
 
-hipError_t launch_backward_batched(const LaunchCtx& ctx, int ncubes, const OutPtrs* fwds,
-                                   const float2* const* gas, float2* const* gxs, size_t lds, int threads,
-                                   hipStream_t st) {
+hipError_t launch_backward_batched(const LaunchCtx& ctx, const KernelKey& key, const int32_t* order, int ncubes,
+                                   const OutPtrs* fwds, const float2* const* gas, float2* const* gxs, size_t lds,
+                                   int threads, hipStream_t st) {
   OutPtrs none{};
-  hipLaunchKernelGGL(k_backward, dim3(ncubes), dim3(threads), lds, st, ctx.descs, -1, none,
-                     (const float2*)nullptr, (float2*)nullptr, fwds, gas, gxs, ctx.sched, ctx.tw);
+  FPS_DISPATCH_D(key.D, FPS_DISPATCH_B(key.pow2, kP, {
+    hipLaunchKernelGGL((k_backward<kD, kP>), dim3(ncubes), dim3(threads), lds, st, ctx.descs, -1, none,
+                       (const float2*)nullptr, (float2*)nullptr, order, fwds, gas, gxs, ctx.sched, ctx.tw);
+  }))
   return hipGetLastError();
 }
-
-const void* kernel_solve_batched() { return (const void*)k_solve_batched; }
-const void* kernel_solve_plain() { return (const void*)k_solve_plain; }
-const void* kernel_lines() { return (const void*)k_lines; }
-const void* kernel_backward() { return (const void*)k_backward; }
 
 }  // namespace fpssft

@@ -14,28 +14,37 @@ struct LaunchCtx {
   const float2* tw;
 };
 
-hipError_t launch_lines_single(const LaunchCtx& ctx, int cube, const float2* x, int t0, int count,
-                               int G, float2* out, size_t lds, int threads, hipStream_t st);
-hipError_t launch_lines_items(const LaunchCtx& ctx, const LineItem* items, int nitems,
-                              const float2* const* xs, float2* out, size_t lds, int threads,
-                              hipStream_t st);
-hipError_t launch_solve_plain(const LaunchCtx& ctx, int cube, const float2* x, const OutPtrs& out,
-                              const float2* pre, int pre_count, size_t lds, int threads, hipStream_t st);
-hipError_t launch_solve_batched(const LaunchCtx& ctx, const float2* const* xs, const OutPtrs* outs,
-                                const int32_t* order, int ncubes, int* queue, int grid, size_t lds,
-                                int threads, hipStream_t st);
-hipError_t launch_zero_single(float2* p, int64_t n, hipStream_t st);
-hipError_t launch_zero_multi(float2* const* bufs, const int64_t* lens, int nbufs, int64_t maxlen,
-                             hipStream_t st);
-hipError_t launch_backward_single(const LaunchCtx& ctx, int cube, const OutPtrs& fwd, const float2* ga,
-                                  float2* gx, size_t lds, int threads, hipStream_t st);
-hipError_t launch_backward_batched(const LaunchCtx& ctx, int ncubes, const OutPtrs* fwds,
-                                   const float2* const* gas, float2* const* gxs, size_t lds, int threads,
-                                   hipStream_t st);
+// Which kernel instantiation serves a cube: dimension count, power-of-two
+// line length (all N_k are then powers of two), records kept in LDS.
+struct KernelKey {
+  int D;
+  bool pow2;
+  bool rec_lds;
+  bool operator==(const KernelKey& o) const { return D == o.D && pow2 == o.pow2 && rec_lds == o.rec_lds; }
+};
 
-const void* kernel_solve_batched();
-const void* kernel_solve_plain();
-const void* kernel_lines();
-const void* kernel_backward();
+enum class KernelKind { kLines, kSolvePlain, kSolveBatched, kBackward };
+
+const void* kernel_ptr(KernelKind kind, const KernelKey& key);
+
+hipError_t launch_lines_single(const LaunchCtx& ctx, const KernelKey& key, int cube, const float2* x, int t0,
+                               int count, float2* out, int maxL, size_t lds, int threads, hipStream_t st);
+hipError_t launch_lines_items(const LaunchCtx& ctx, const KernelKey& key, const LineItem* items,
+                              const int32_t* ranges, int* queues, int grid, const float2* const* xs, float2* out,
+                              int maxL, size_t lds, int threads, hipStream_t st);
+hipError_t launch_solve_plain(const LaunchCtx& ctx, const KernelKey& key, int cube, const float2* x,
+                              const OutPtrs& out, const float2* pre, int pre_count, size_t lds, int threads,
+                              hipStream_t st);
+hipError_t launch_reset(int* p, int n, hipStream_t st);
+hipError_t launch_solve_batched(const LaunchCtx& ctx, const KernelKey& key, const float2* const* xs,
+                                const OutPtrs* outs, const int32_t* order, int ncubes, int* queue, int grid,
+                                size_t lds, int threads, hipStream_t st);
+hipError_t launch_zero_single(float2* p, int64_t n, hipStream_t st);
+hipError_t launch_zero_multi(float2* const* bufs, const int64_t* lens, int nbufs, int64_t maxlen, hipStream_t st);
+hipError_t launch_backward_single(const LaunchCtx& ctx, const KernelKey& key, int cube, const OutPtrs& fwd,
+                                  const float2* ga, float2* gx, size_t lds, int threads, hipStream_t st);
+hipError_t launch_backward_batched(const LaunchCtx& ctx, const KernelKey& key, const int32_t* order, int ncubes,
+                                   const OutPtrs* fwds, const float2* const* gas, float2* const* gxs, size_t lds,
+                                   int threads, hipStream_t st);
 
 }  // namespace fpssft

@@ -206,15 +206,35 @@ fpssft_status hip_status(hipError_t e) {
 
 }  // namespace
 
+// Cubes served by one kernel instantiation: a contiguous slice of the
+// order array (longest lines first) and of the line-FFT item list.
+struct Group {
+  fpssft::KernelKey key;
+  int first = 0;        // into order[]
+  int count = 0;
+  int item_first = 0;   // into items[]
+  int item_count = 0;
+  int grid = 0;         // persistent solve grid
+  size_t lds_solve = 0;
+  size_t lds_bwd = 0;
+  size_t lds_lines = 0;
+  int lines_grid = 0;   // persistent line-FFT grid (multiple of 8)
+  int32_t maxL = 1;
+  int64_t max_N = 0;
+};
+
 struct fpssft_plan_st {
   int device = 0;
   int B = 0;
   int ncu = 0;
   size_t lds_max = 0;
   fpssft_tuning tune{};
+  bool rec_lds = true;
   std::vector<CubeDesc> descs;
   std::vector<int32_t> sched;
   std::vector<float2> tw;
+  std::vector<int> group_of;   // per cube
+  std::vector<Group> groups;
   int64_t spec_elems = 0;
   LaunchCtx ctx{};
   CubeDesc* d_descs = nullptr;
@@ -222,15 +242,9 @@ struct fpssft_plan_st {
   float2* d_tw = nullptr;
   // plain path
   float2* d_pre = nullptr;
-  int32_t pre_iters = 0;
-  int32_t lines_G_single = 1;
-  size_t lds_lines_single = 0;
-  size_t lds_solve = 0;
-  size_t lds_bwd = 0;
   // batched path
   int32_t* d_order = nullptr;
   int* d_queue = nullptr;
-  int grid_batched = 0;
   StagedTable xs_tab, outs_tab, ga_tab, gx_tab, len_tab;
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
@@ -238,29 +252,33 @@ struct fpssft_plan_st {
   // line-FFT over the whole budget
   std::vector<LineItem> items;
   LineItem* d_items = nullptr;
-  size_t lds_lines_all = 0;
+  std::vector<int32_t> ranges;  // per group: 8 x [lo, hi) item ranges, one per XCD
+  int32_t* d_ranges = nullptr;
+  int* d_lqueue = nullptr;      // per group: 8 queue counters
   int64_t max_N = 0;
-  int32_t maxL = 1;
-  int32_t maxD = 1;
 };
 
 namespace {
 
 size_t solve_lds_bytes(const CubeDesc& c, int rec_lds) {
-  size_t b = 2 * (size_t)(c.D + 1) * c.L * sizeof(float2);
+  size_t b = (2 * (size_t)(c.D + 1) + 1) * c.L * sizeof(float2);
   b += (size_t)rec_lds * sizeof(float2) + (size_t)rec_lds * c.D * sizeof(int32_t);
   b += 64 * sizeof(int);
   return b;
 }
 
 size_t bwd_lds_bytes(const CubeDesc& c) {
-  return 2 * (size_t)c.L * sizeof(float2) + (size_t)c.max_k * sizeof(float2) + 64;
+  return 3 * (size_t)c.L * sizeof(float2) + (size_t)c.max_k * sizeof(float2) + 64;
 }
 
-int lines_group(const CubeDesc& c, int lines_wg, size_t lds_max) {
-  int G = std::max(1, lines_wg / (c.D + 1));
-  while (G > 1 && 2 * (size_t)G * (c.D + 1) * c.L * sizeof(float2) > lds_max) --G;
-  return G;
+// Line-FFT work-group LDS: two line buffers and the twiddle table.
+size_t lines_lds_bytes(int D, int L) { return (2 * (size_t)(D + 1) + 1) * L * sizeof(float2); }
+
+size_t lines_single_lds_bytes(const CubeDesc& c) { return lines_lds_bytes(c.D, c.L); }
+
+fpssft::KernelKey key_of(const fpssft_plan_t p, int c) {
+  const CubeDesc& cd = p->descs[c];
+  return fpssft::KernelKey{cd.D, cd.Lmask >= 0, p->rec_lds};
 }
 
 void destroy_plan(fpssft_plan_t p) {
@@ -282,6 +300,8 @@ void destroy_plan(fpssft_plan_t p) {
   hipFree(p->d_order);
   hipFree(p->d_queue);
   hipFree(p->d_items);
+  hipFree(p->d_ranges);
+  hipFree(p->d_lqueue);
   delete p;
 }
 
@@ -296,21 +316,22 @@ fpssft_status build_plan(const fpssft_desc* descs, int32_t batch, const fpssft_t
   if (v <= 2048) return FPSSFT_ERR_UNSUPPORTED;
   p->lds_max = (size_t)v - 1024;
   p->B = batch;
-  fpssft_tuning tn{256, 8, 8, 16};
+  fpssft_tuning tn{256, 8, 8, 4, 256};
   if (tuning) {
     if (tuning->block_threads) tn.block_threads = tuning->block_threads;
     if (tuning->max_radix) tn.max_radix = tuning->max_radix;
     if (tuning->chunk_iters >= 0) tn.chunk_iters = tuning->chunk_iters;
     if (tuning->lines_wg) tn.lines_wg = tuning->lines_wg;
+    if (tuning->lines_threads) tn.lines_threads = tuning->lines_threads;
   }
   if (tn.block_threads < 64 || tn.block_threads > 1024 || tn.block_threads % 64) return FPSSFT_ERR_INVALID_ARG;
+  if (tn.lines_threads < 64 || tn.lines_threads > 1024 || tn.lines_threads % 64) return FPSSFT_ERR_INVALID_ARG;
   if (tn.max_radix != 2 && tn.max_radix != 4 && tn.max_radix != 8) return FPSSFT_ERR_INVALID_ARG;
   if (tn.lines_wg < 1) return FPSSFT_ERR_INVALID_ARG;
   p->tune = tn;
 
   std::map<int32_t, int32_t> tw_off;
   p->descs.resize(batch);
-  int32_t max_pre_elems_T = 0;
   int64_t max_pre = 0;
   for (int32_t c = 0; c < batch; ++c) {
     const fpssft_desc& d = descs[c];
@@ -357,44 +378,118 @@ fpssft_status build_plan(const fpssft_desc* descs, int32_t batch, const fpssft_t
       it = tw_off.emplace(L, off).first;
     }
     cd.tw_off = it->second;
-    // Records in LDS when spectra + records fit; otherwise the output arrays.
-    cd.rec_lds = solve_lds_bytes(cd, cd.max_k) <= p->lds_max ? cd.max_k : 0;
-    if (solve_lds_bytes(cd, cd.rec_lds) > p->lds_max) return FPSSFT_ERR_UNSUPPORTED;
     cd.spec_off = p->spec_elems;
     p->spec_elems += (int64_t)T * (d.ndim + 1) * L;
     const int32_t pre_T = std::min(T, tn.chunk_iters);
     max_pre = std::max<int64_t>(max_pre, (int64_t)pre_T * (d.ndim + 1) * L);
-    max_pre_elems_T = std::max(max_pre_elems_T, pre_T);
-    p->lds_solve = std::max(p->lds_solve, solve_lds_bytes(cd, cd.rec_lds));
-    p->lds_bwd = std::max(p->lds_bwd, bwd_lds_bytes(cd));
     p->max_N = std::max(p->max_N, cd.N);
-    p->maxL = std::max(p->maxL, L);
-    p->maxD = std::max(p->maxD, (int32_t)d.ndim);
+    if (solve_lds_bytes(cd, 0) > p->lds_max || lines_single_lds_bytes(cd) > p->lds_max)
+      return FPSSFT_ERR_UNSUPPORTED;
+    // The record list stays in LDS when every cube's spectra and records fit.
+    if (solve_lds_bytes(cd, cd.max_k) > p->lds_max) p->rec_lds = false;
     p->descs[c] = cd;
   }
-  // Line-FFT work-group shapes: one G for single-cube calls (largest cube),
-  // per-cube G in the all-cubes item list.
-  {
-    // Single-cube calls (the plain path's chunk, spectra export): one
-    // iteration per work-group, for the most parallelism on one cube.
-    p->lines_G_single = 1;
-    p->lds_lines_single = 2 * (size_t)(p->maxD + 1) * p->maxL * sizeof(float2);
-    if (p->lds_lines_single > p->lds_max) return FPSSFT_ERR_UNSUPPORTED;
-  }
+  for (auto& cd : p->descs) cd.rec_lds = p->rec_lds ? cd.max_k : 0;
+
+  // Group cubes by kernel instantiation; within a group, longest lines first
+  // (the per-iteration cost grows with (D+1) L), ties by index.
+  p->group_of.assign(batch, -1);
   for (int32_t c = 0; c < batch; ++c) {
-    const CubeDesc& cd = p->descs[c];
-    const int G = lines_group(cd, tn.lines_wg, p->lds_max);
-    p->lds_lines_all = std::max(p->lds_lines_all, 2 * (size_t)G * (cd.D + 1) * cd.L * sizeof(float2));
-    for (int32_t t = 0; t < cd.T; t += G) {
-      LineItem li{};
-      li.cube = c;
-      li.t0 = t;
-      li.count = std::min(G, cd.T - t);
-      li.out_off = cd.spec_off + (int64_t)t * (cd.D + 1) * cd.L;
-      p->items.push_back(li);
+    const fpssft::KernelKey k = key_of(p, c);
+    int gi = -1;
+    for (size_t i = 0; i < p->groups.size(); ++i)
+      if (p->groups[i].key == k) gi = (int)i;
+    if (gi < 0) {
+      Group g;
+      g.key = k;
+      p->groups.push_back(g);
+      gi = (int)p->groups.size() - 1;
     }
+    p->group_of[c] = gi;
   }
-  p->pre_iters = max_pre_elems_T;
+  std::vector<int32_t> order(batch);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+    if (p->group_of[a] != p->group_of[b]) return p->group_of[a] < p->group_of[b];
+    const int64_t ca = (int64_t)(p->descs[a].D + 1) * p->descs[a].L;
+    const int64_t cb = (int64_t)(p->descs[b].D + 1) * p->descs[b].L;
+    return ca > cb;
+  });
+  const int threads = tn.block_threads;
+  for (size_t gi = 0; gi < p->groups.size(); ++gi) {
+    Group& g = p->groups[gi];
+    g.first = -1;
+    for (int i = 0; i < batch; ++i) {
+      if (p->group_of[order[i]] != (int)gi) continue;
+      if (g.first < 0) g.first = i;
+      ++g.count;
+      const CubeDesc& cd = p->descs[order[i]];
+      g.lds_solve = std::max(g.lds_solve, solve_lds_bytes(cd, cd.rec_lds));
+      g.lds_bwd = std::max(g.lds_bwd, bwd_lds_bytes(cd));
+      g.max_N = std::max(g.max_N, cd.N);
+    }
+    // Line-FFT items of this group, cube by cube in order: runs of at most
+    // lines_wg consecutive iterations.
+    g.item_first = (int)p->items.size();
+    for (int i = g.first; i < g.first + g.count; ++i) {
+      const int32_t c = order[i];
+      const CubeDesc& cd = p->descs[c];
+      g.maxL = std::max(g.maxL, cd.L);
+      for (int32_t t = 0; t < cd.T; t += tn.lines_wg) {
+        LineItem li{};
+        li.cube = c;
+        li.t0 = t;
+        li.count = std::min(tn.lines_wg, cd.T - t);
+        li.out_off = cd.spec_off + (int64_t)t * (cd.D + 1) * cd.L;
+        p->items.push_back(li);
+      }
+    }
+    g.item_count = (int)p->items.size() - g.item_first;
+    g.lds_lines = lines_lds_bytes(g.key.D, g.maxL);
+    if (g.lds_lines > p->lds_max) return FPSSFT_ERR_UNSUPPORTED;
+    // Eight contiguous item ranges of about equal work ((D+1) L per iteration).
+    {
+      int64_t total = 0;
+      for (int i = 0; i < g.item_count; ++i) {
+        const LineItem& li = p->items[g.item_first + i];
+        total += (int64_t)li.count * (p->descs[li.cube].D + 1) * p->descs[li.cube].L;
+      }
+      int64_t acc = 0;
+      int x = 0;
+      int lo = 0;
+      for (int i = 0; i < g.item_count && x < 7; ++i) {
+        const LineItem& li = p->items[g.item_first + i];
+        acc += (int64_t)li.count * (p->descs[li.cube].D + 1) * p->descs[li.cube].L;
+        if (acc * 8 >= total * (x + 1)) {
+          p->ranges.push_back(lo);
+          p->ranges.push_back(i + 1);
+          lo = i + 1;
+          ++x;
+        }
+      }
+      for (; x < 8; ++x) {
+        p->ranges.push_back(lo);
+        p->ranges.push_back(x == 7 ? g.item_count : lo);
+        lo = x == 7 ? g.item_count : lo;
+      }
+    }
+    for (fpssft::KernelKind kind : {fpssft::KernelKind::kLines, fpssft::KernelKind::kSolvePlain,
+                                    fpssft::KernelKind::kSolveBatched, fpssft::KernelKind::kBackward}) {
+      HIP_TRY(hipFuncSetAttribute(fpssft::kernel_ptr(kind, g.key), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)p->lds_max));
+    }
+    int occ = 0;
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &occ, fpssft::kernel_ptr(fpssft::KernelKind::kSolveBatched, g.key), threads, g.lds_solve));
+    if (occ < 1) return FPSSFT_ERR_UNSUPPORTED;
+    g.grid = (int)std::max<int64_t>(1, std::min<int64_t>(g.count, (int64_t)occ * p->ncu));
+    int locc = 0;
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &locc, fpssft::kernel_ptr(fpssft::KernelKind::kLines, g.key), tn.lines_threads, g.lds_lines));
+    if (locc < 1) return FPSSFT_ERR_UNSUPPORTED;
+    const int64_t lg = std::min<int64_t>((int64_t)locc * p->ncu, ((int64_t)g.item_count + 7) / 8 * 8);
+    g.lines_grid = (int)std::max<int64_t>(8, lg / 8 * 8);
+  }
 
   HIP_TRY(hipMalloc(&p->d_descs, sizeof(CubeDesc) * batch));
   HIP_TRY(hipMemcpy(p->d_descs, p->descs.data(), sizeof(CubeDesc) * batch, hipMemcpyHostToDevice));
@@ -403,21 +498,16 @@ fpssft_status build_plan(const fpssft_desc* descs, int32_t batch, const fpssft_t
   HIP_TRY(hipMalloc(&p->d_tw, sizeof(float2) * p->tw.size()));
   HIP_TRY(hipMemcpy(p->d_tw, p->tw.data(), sizeof(float2) * p->tw.size(), hipMemcpyHostToDevice));
   if (max_pre > 0) HIP_TRY(hipMalloc(&p->d_pre, sizeof(float2) * max_pre));
-  // Batched order: longest lines first (the per-iteration cost grows with
-  // (D+1) L), ties by index.
-  std::vector<int32_t> order(batch);
-  std::iota(order.begin(), order.end(), 0);
-  std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
-    const int64_t ca = (int64_t)(p->descs[a].D + 1) * p->descs[a].L;
-    const int64_t cb = (int64_t)(p->descs[b].D + 1) * p->descs[b].L;
-    return ca > cb;
-  });
   HIP_TRY(hipMalloc(&p->d_order, sizeof(int32_t) * batch));
   HIP_TRY(hipMemcpy(p->d_order, order.data(), sizeof(int32_t) * batch, hipMemcpyHostToDevice));
-  HIP_TRY(hipMalloc(&p->d_queue, sizeof(int) * 4));
-  HIP_TRY(hipMemset(p->d_queue, 0, sizeof(int) * 4));
+  HIP_TRY(hipMalloc(&p->d_queue, sizeof(int) * std::max<size_t>(p->groups.size(), 1)));
+  HIP_TRY(hipMemset(p->d_queue, 0, sizeof(int) * std::max<size_t>(p->groups.size(), 1)));
   HIP_TRY(hipMalloc(&p->d_items, sizeof(LineItem) * std::max<size_t>(p->items.size(), 1)));
   HIP_TRY(hipMemcpy(p->d_items, p->items.data(), sizeof(LineItem) * p->items.size(), hipMemcpyHostToDevice));
+  HIP_TRY(hipMalloc(&p->d_ranges, sizeof(int32_t) * p->ranges.size()));
+  HIP_TRY(hipMemcpy(p->d_ranges, p->ranges.data(), sizeof(int32_t) * p->ranges.size(), hipMemcpyHostToDevice));
+  HIP_TRY(hipMalloc(&p->d_lqueue, sizeof(int) * 8 * p->groups.size()));
+  HIP_TRY(hipMemset(p->d_lqueue, 0, sizeof(int) * 8 * p->groups.size()));
   HIP_TRY(p->xs_tab.init(sizeof(void*) * batch));
   HIP_TRY(p->outs_tab.init(sizeof(OutPtrs) * batch));
   HIP_TRY(p->ga_tab.init(sizeof(void*) * batch));
@@ -426,18 +516,6 @@ fpssft_status build_plan(const fpssft_desc* descs, int32_t batch, const fpssft_t
   p->ctx.descs = p->d_descs;
   p->ctx.sched = p->d_sched;
   p->ctx.tw = p->d_tw;
-
-  const int threads = tn.block_threads;
-  for (const void* fn : {fpssft::kernel_solve_batched(), fpssft::kernel_solve_plain(), fpssft::kernel_lines(),
-                         fpssft::kernel_backward()}) {
-    HIP_TRY(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p->lds_max));
-  }
-  int occ = 0;
-  HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fpssft::kernel_solve_batched(), threads,
-                                                       p->lds_solve));
-  if (occ < 1) return FPSSFT_ERR_UNSUPPORTED;
-  p->grid_batched = std::min<int64_t>(batch, (int64_t)occ * p->ncu);
-  if (p->grid_batched < 1) p->grid_batched = 1;
   HIP_TRY(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
   return FPSSFT_OK;
 }
@@ -481,6 +559,7 @@ fpssft_status fpssft_validate(const fpssft_desc* desc, int32_t* line_length, int
 }
 
 fpssft_status fpssft_schedule_generate(const fpssft_desc* desc, int32_t T, int32_t* alpha_tau) {
+  if (!desc) return FPSSFT_ERR_INVALID_ARG;
   int32_t L, Tm;
   fpssft_desc d = *desc;
   d.schedule = nullptr;
@@ -542,13 +621,15 @@ fpssft_status fpssft_execute(fpssft_plan_t p, int32_t cube, const void* x, const
   if (!p || cube < 0 || cube >= p->B || !x || !check_out(out)) return FPSSFT_ERR_INVALID_ARG;
   hipStream_t st = (hipStream_t)stream;
   const CubeDesc& cd = p->descs[cube];
+  const fpssft::KernelKey key = key_of(p, cube);
+  const Group& g = p->groups[p->group_of[cube]];
   const int pre = std::min(cd.T, p->tune.chunk_iters);
   if (pre > 0) {
-    HIP_TRY(fpssft::launch_lines_single(p->ctx, cube, (const float2*)x, 0, pre, p->lines_G_single, p->d_pre,
-                                        p->lds_lines_single, p->tune.block_threads, st));
+    HIP_TRY(fpssft::launch_lines_single(p->ctx, key, cube, (const float2*)x, 0, pre, p->d_pre, cd.L,
+                                        lines_single_lds_bytes(cd), p->tune.lines_threads, st));
   }
-  HIP_TRY(fpssft::launch_solve_plain(p->ctx, cube, (const float2*)x, to_ptrs(*out), p->d_pre, pre, p->lds_solve,
-                                     p->tune.block_threads, st));
+  HIP_TRY(fpssft::launch_solve_plain(p->ctx, key, cube, (const float2*)x, to_ptrs(*out), p->d_pre, pre,
+                                     g.lds_solve, p->tune.block_threads, st));
   return FPSSFT_OK;
 }
 
@@ -564,16 +645,24 @@ fpssft_status fpssft_execute_batched(fpssft_plan_t p, const void* const* xs, con
   HIP_TRY(p->xs_tab.update(xs, st));
   HIP_TRY(p->outs_tab.update(op.data(), st));
   if (!p->gexec) {
+    // One graph: reset every group's queue counter, then one persistent
+    // launch per group.
     HIP_TRY(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
-    hipError_t e = fpssft::launch_solve_batched(p->ctx, (const float2* const*)p->xs_tab.dev,
-                                                (const OutPtrs*)p->outs_tab.dev, p->d_order, p->B, p->d_queue,
-                                                p->grid_batched, p->lds_solve, p->tune.block_threads,
-                                                p->cap_stream);
-    hipGraph_t g = nullptr;
-    hipError_t e2 = hipStreamEndCapture(p->cap_stream, &g);
-    if (e != hipSuccess) return hip_status(e);
+    hipError_t e = fpssft::launch_reset(p->d_queue, (int)p->groups.size(), p->cap_stream);
+    for (size_t gi = 0; e == hipSuccess && gi < p->groups.size(); ++gi) {
+      const Group& g = p->groups[gi];
+      e = fpssft::launch_solve_batched(p->ctx, g.key, (const float2* const*)p->xs_tab.dev,
+                                       (const OutPtrs*)p->outs_tab.dev, p->d_order + g.first, g.count,
+                                       p->d_queue + gi, g.grid, g.lds_solve, p->tune.block_threads, p->cap_stream);
+    }
+    hipGraph_t graph = nullptr;
+    hipError_t e2 = hipStreamEndCapture(p->cap_stream, &graph);
+    if (e != hipSuccess) {
+      if (graph) hipGraphDestroy(graph);
+      return hip_status(e);
+    }
     if (e2 != hipSuccess) return hip_status(e2);
-    p->graph = g;
+    p->graph = graph;
     HIP_TRY(hipGraphInstantiate(&p->gexec, p->graph, nullptr, nullptr, 0));
   }
   HIP_TRY(hipGraphLaunch(p->gexec, st));
@@ -586,8 +675,8 @@ fpssft_status fpssft_lines_fft(fpssft_plan_t p, int32_t cube, const void* x, int
   const CubeDesc& cd = p->descs[cube];
   if (t0 < 0 || count < 0 || (int64_t)t0 + count > cd.T) return FPSSFT_ERR_INVALID_ARG;
   if (count == 0) return FPSSFT_OK;
-  HIP_TRY(fpssft::launch_lines_single(p->ctx, cube, (const float2*)x, t0, count, p->lines_G_single,
-                                      (float2*)spectra, p->lds_lines_single, p->tune.block_threads,
+  HIP_TRY(fpssft::launch_lines_single(p->ctx, key_of(p, cube), cube, (const float2*)x, t0, count,
+                                      (float2*)spectra, cd.L, lines_single_lds_bytes(cd), p->tune.lines_threads,
                                       (hipStream_t)stream));
   return FPSSFT_OK;
 }
@@ -598,32 +687,37 @@ fpssft_status fpssft_lines_fft_all(fpssft_plan_t p, const void* const* xs, void*
     if (!xs[c]) return FPSSFT_ERR_INVALID_ARG;
   hipStream_t st = (hipStream_t)stream;
   HIP_TRY(p->xs_tab.update(xs, st));
-  HIP_TRY(fpssft::launch_lines_items(p->ctx, p->d_items, (int)p->items.size(),
-                                     (const float2* const*)p->xs_tab.dev, (float2*)spectra, p->lds_lines_all,
-                                     p->tune.block_threads, st));
+  HIP_TRY(fpssft::launch_reset(p->d_lqueue, 8 * (int)p->groups.size(), st));
+  for (size_t gi = 0; gi < p->groups.size(); ++gi) {
+    const Group& g = p->groups[gi];
+    if (g.item_count == 0) continue;
+    HIP_TRY(fpssft::launch_lines_items(p->ctx, g.key, p->d_items + g.item_first, p->d_ranges + 16 * gi,
+                                       p->d_lqueue + 8 * gi, g.lines_grid, (const float2* const*)p->xs_tab.dev,
+                                       (float2*)spectra, g.maxL, g.lds_lines, p->tune.lines_threads, st));
+  }
   return FPSSFT_OK;
 }
 
 fpssft_status fpssft_amp_backward(fpssft_plan_t p, int32_t cube, const fpssft_out* fwd, const void* grad_amps,
                                   void* grad_x, void* stream) {
   if (!p || cube < 0 || cube >= p->B || !check_out(fwd) || !grad_amps || !grad_x) return FPSSFT_ERR_INVALID_ARG;
-  if (p->lds_bwd > p->lds_max) return FPSSFT_ERR_UNSUPPORTED;
-  hipStream_t st = (hipStream_t)stream;
   const CubeDesc& cd = p->descs[cube];
+  if (bwd_lds_bytes(cd) > p->lds_max) return FPSSFT_ERR_UNSUPPORTED;
+  hipStream_t st = (hipStream_t)stream;
   HIP_TRY(fpssft::launch_zero_single((float2*)grad_x, cd.N, st));
-  HIP_TRY(fpssft::launch_backward_single(p->ctx, cube, to_ptrs(*fwd), (const float2*)grad_amps,
-                                         (float2*)grad_x, p->lds_bwd, p->tune.block_threads, st));
+  HIP_TRY(fpssft::launch_backward_single(p->ctx, key_of(p, cube), cube, to_ptrs(*fwd), (const float2*)grad_amps,
+                                         (float2*)grad_x, bwd_lds_bytes(cd), p->tune.block_threads, st));
   return FPSSFT_OK;
 }
 
 fpssft_status fpssft_amp_backward_batched(fpssft_plan_t p, const fpssft_out* fwds, const void* const* grad_amps,
                                           void* const* grad_xs, void* stream) {
   if (!p || !fwds || !grad_amps || !grad_xs) return FPSSFT_ERR_INVALID_ARG;
-  if (p->lds_bwd > p->lds_max) return FPSSFT_ERR_UNSUPPORTED;
   std::vector<OutPtrs> op(p->B);
   std::vector<int64_t> lens(p->B);
   for (int c = 0; c < p->B; ++c) {
     if (!check_out(&fwds[c]) || !grad_amps[c] || !grad_xs[c]) return FPSSFT_ERR_INVALID_ARG;
+    if (bwd_lds_bytes(p->descs[c]) > p->lds_max) return FPSSFT_ERR_UNSUPPORTED;
     op[c] = to_ptrs(fwds[c]);
     lens[c] = p->descs[c].N;
   }
@@ -634,9 +728,11 @@ fpssft_status fpssft_amp_backward_batched(fpssft_plan_t p, const fpssft_out* fwd
   HIP_TRY(p->len_tab.update(lens.data(), st));
   HIP_TRY(fpssft::launch_zero_multi((float2* const*)p->gx_tab.dev, (const int64_t*)p->len_tab.dev, p->B,
                                     p->max_N, st));
-  HIP_TRY(fpssft::launch_backward_batched(p->ctx, p->B, (const OutPtrs*)p->outs_tab.dev,
-                                          (const float2* const*)p->ga_tab.dev, (float2* const*)p->gx_tab.dev,
-                                          p->lds_bwd, p->tune.block_threads, st));
+  for (const Group& g : p->groups) {
+    HIP_TRY(fpssft::launch_backward_batched(p->ctx, g.key, p->d_order + g.first, g.count,
+                                            (const OutPtrs*)p->outs_tab.dev, (const float2* const*)p->ga_tab.dev,
+                                            (float2* const*)p->gx_tab.dev, g.lds_bwd, p->tune.block_threads, st));
+  }
   return FPSSFT_OK;
 }
 

@@ -1,0 +1,176 @@
+"""Autotuner for the launch shapes of the FPS-SFT kernels.
+
+Each knob group is tuned on the kernel it drives, on the caller's workload,
+with HIP events around repeated launches:
+
+  solve    block_threads x max_radix  -> persistent batched solve (one
+           graph replay over all cubes)
+  lines    lines_wg x lines_threads   -> line gather + FFT over every cube's
+           whole iteration budget
+  plain    chunk_iters                -> plain per-cube path over a subset
+
+Every candidate's outputs are compared with the first candidate's (identical
+frequencies, bins, iteration counts and outcomes); a candidate that changes a
+decision is rejected. The result is stored as JSON keyed by the GPU
+architecture name and read back with `load`.
+
+    python -m paper_1711_11407_amd.tune            # the batched workload
+"""
+from __future__ import annotations
+
+import argparse
+import itertools
+import json
+import os
+import sys
+import time
+
+DEFAULT_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning.json")
+
+SOLVE_GRID = dict(block_threads=(64, 128, 256, 512), max_radix=(4, 8))
+LINES_GRID = dict(lines_wg=(1, 2, 4, 8), lines_threads=(64, 128, 256, 512))
+PLAIN_GRID = dict(chunk_iters=(0, 2, 4, 8, 16))
+
+
+def _arch() -> str:
+    import torch
+    props = torch.cuda.get_device_properties(0)
+    return getattr(props, "gcnArchName", "unknown").split(":")[0]
+
+
+def _time_ms(torch, fn, reps: int, warmup: int = 2) -> float:
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def _decisions(outs):
+    import torch
+    info = torch.stack([o.info for o in outs]).cpu()
+    sig = [tuple(info[c, :3].tolist()) for c in range(len(outs))]
+    freqs = [o.freqs[: int(info[c, 0])].cpu() for c, o in enumerate(outs)]
+    bins = [o.rec_bin[: int(info[c, 0])].cpu() for c, o in enumerate(outs)]
+    return sig, freqs, bins
+
+
+def _same(a, b) -> bool:
+    if a[0] != b[0]:
+        return False
+    return all((x == y).all() for x, y in zip(a[1], b[1])) and all((x == y).all() for x, y in zip(a[2], b[2]))
+
+
+def tune(specs, xs, reps: int = 10, plain_cubes: int = 128, log=print) -> dict:
+    """Best launch shapes for the workload (specs, device inputs xs)."""
+    import torch
+    from . import Plan
+
+    best = {}
+    results = {"solve": [], "lines": [], "plain": []}
+
+    # 1. persistent batched solve
+    ref = None
+    best_ms = None
+    for bt, mr in itertools.product(SOLVE_GRID["block_threads"], SOLVE_GRID["max_radix"]):
+        tn = dict(block_threads=bt, max_radix=mr)
+        plan = Plan(specs, tuning=tn)
+        bound = plan.bind(xs)
+        ms = _time_ms(torch, bound.run_batched, reps)
+        dec = _decisions(bound.outs)
+        ok = ref is None or _same(ref, dec)
+        ref = ref or dec
+        results["solve"].append(dict(tn, ms=round(ms, 4), same_decisions=ok))
+        log(f"solve {tn}: {ms * 1e3:.1f} us{'' if ok else '  (decisions differ: rejected)'}")
+        if ok and (best_ms is None or ms < best_ms):
+            best_ms, best["solve"] = ms, tn
+        del plan, bound
+
+    # 2. line gather + FFT
+    best_ms = None
+    for wg, lt in itertools.product(LINES_GRID["lines_wg"], LINES_GRID["lines_threads"]):
+        tn = dict(best["solve"], lines_wg=wg, lines_threads=lt)
+        plan = Plan(specs, tuning=tn)
+        bound = plan.bind(xs)
+        ms = _time_ms(torch, bound.run_lines_all, reps)
+        results["lines"].append(dict(lines_wg=wg, lines_threads=lt, ms=round(ms, 4)))
+        log(f"lines lines_wg={wg} lines_threads={lt}: {ms * 1e3:.1f} us")
+        if best_ms is None or ms < best_ms:
+            best_ms, best["lines"] = ms, dict(lines_wg=wg, lines_threads=lt)
+        del plan, bound
+
+    # 3. plain per-cube path on a subset
+    sub = list(range(min(plain_cubes, len(specs))))
+    best_ms = None
+    pref = None
+    for ch in PLAIN_GRID["chunk_iters"]:
+        tn = dict(best["solve"], **best["lines"], chunk_iters=ch)
+        plan = Plan([specs[c] for c in sub], tuning=tn)
+        bound = plan.bind([xs[c] for c in sub])
+        ms = _time_ms(torch, bound.run_plain_all, max(1, reps // 5), warmup=1)
+        dec = _decisions(bound.outs)
+        ok = pref is None or _same(pref, dec)
+        pref = pref or dec
+        results["plain"].append(dict(chunk_iters=ch, ms=round(ms, 4), same_decisions=ok))
+        log(f"plain chunk_iters={ch}: {ms * 1e3:.1f} us for {len(sub)} cubes{'' if ok else ' (rejected)'}")
+        if ok and (best_ms is None or ms < best_ms):
+            best_ms, best["plain"] = ms, dict(chunk_iters=ch)
+        del plan, bound
+
+    merged = dict(best["solve"], **best["lines"], **best["plain"])
+    return dict(tuning=merged, results=results)
+
+
+def save(arch: str, workload: str, out: dict, path: str = DEFAULT_PATH) -> None:
+    data = {}
+    if os.path.exists(path):
+        with open(path) as f:
+            data = json.load(f)
+    data.setdefault(arch, {})[workload] = dict(out["tuning"], measured=out["results"],
+                                               date=time.strftime("%Y-%m-%d"))
+    with open(path, "w") as f:
+        json.dump(data, f, indent=1, sort_keys=True)
+
+
+def load(arch: str, workload: str, path: str = DEFAULT_PATH):
+    """Tuned shapes for (arch, workload) as a Plan tuning dict, or None."""
+    try:
+        with open(path) as f:
+            ent = json.load(f).get(arch, {}).get(workload)
+    except FileNotFoundError:
+        return None
+    if not ent:
+        return None
+    keys = ("block_threads", "max_radix", "chunk_iters", "lines_wg", "lines_threads")
+    return {k: ent[k] for k in keys if k in ent}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--reps", type=int, default=10)
+    ap.add_argument("--out", default=DEFAULT_PATH)
+    args = ap.parse_args(argv)
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    sys.path.insert(0, root)
+    import torch
+    import workloads as W
+    from . import CubeSpec
+
+    dev = torch.device("cuda", 0)
+    cubes = W.cfg4()
+    specs = [CubeSpec(c.dims, seed=c.schedule_seed, max_k=512, **W.NOISELESS_THRESH) for c in cubes]
+    xs = [torch.from_numpy(c.x).to(dev) for c in cubes]
+    out = tune(specs, xs, reps=args.reps, log=lambda m: print(m, flush=True))
+    arch = _arch()
+    save(arch, "batched", out, args.out)
+    print(json.dumps({"arch": arch, "tuning": out["tuning"]}), flush=True)
+
+
+if __name__ == "__main__":
+    main()

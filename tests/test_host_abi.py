@@ -100,3 +100,16 @@ def test_plan_without_device_reports_no_device(F):
     with pytest.raises(F.FpsSftError) as e:
         F.Plan([F.CubeSpec((8, 8))])
     assert e.value.status == -5
+
+
+def test_tuning_cache_roundtrip(tmp_path):
+    from paper_1711_11407_amd import tune
+    path = str(tmp_path / "t.json")
+    assert tune.load("gfx950", "batched", path) is None
+    out = dict(tuning=dict(block_threads=128, max_radix=4, chunk_iters=2, lines_wg=4, lines_threads=256),
+               results={"solve": []})
+    tune.save("gfx950", "batched", out, path)
+    tune.save("gfx942", "batched", dict(out, tuning=dict(block_threads=64)), path)
+    assert tune.load("gfx950", "batched", path) == out["tuning"]
+    assert tune.load("gfx942", "batched", path) == dict(block_threads=64)
+    assert tune.load("gfx950", "other", path) is None
