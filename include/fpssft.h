@@ -101,7 +101,7 @@ typedef struct {
 /* Launch-shape choices of the autotuner (0 = library default; chunk_iters
  * is taken as given when >= 0, so pass -1 for its default).
  *  block_threads  threads per work-group of the solve and adjoint kernels
- *                 (64..1024, multiple of 64)
+ *                 (64..512, multiple of 64)
  *  max_radix      largest FFT radix used for power-of-two factors (2, 4, 8)
  *  chunk_iters    iterations the plain path gathers and transforms ahead
  *                 in parallel before its sequential decode (>= 0)

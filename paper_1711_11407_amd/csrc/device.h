@@ -144,6 +144,116 @@ __device__ __forceinline__ void dft8(float2* v) {
   v[7] = c_sub(e3, t3);
 }
 
+// 16-point DFT as 4 x 4: n = 4 n1 + n2, k = k1 + 4 k2.
+__device__ __forceinline__ void dft16(float2* v) {
+  const float c1 = 0.92387953251128675613f, s1 = 0.38268343236508977173f, h = 0.70710678118654752440f;
+  float2 T[16];
+#pragma unroll
+  for (int n2 = 0; n2 < 4; ++n2) {
+    float2 a0 = v[n2], a1 = v[4 + n2], a2 = v[8 + n2], a3 = v[12 + n2];
+    dft4(a0, a1, a2, a3);
+    T[n2 * 4 + 0] = a0;
+    T[n2 * 4 + 1] = a1;
+    T[n2 * 4 + 2] = a2;
+    T[n2 * 4 + 3] = a3;
+  }
+  // W16^m for m = n2 k1: 1, 2, 3, 2, 4, 6, 3, 6, 9
+  T[1 * 4 + 1] = c_mul(T[1 * 4 + 1], make_float2(c1, -s1));
+  T[1 * 4 + 2] = c_mul(T[1 * 4 + 2], make_float2(h, -h));
+  T[1 * 4 + 3] = c_mul(T[1 * 4 + 3], make_float2(s1, -c1));
+  T[2 * 4 + 1] = c_mul(T[2 * 4 + 1], make_float2(h, -h));
+  T[2 * 4 + 2] = make_float2(T[2 * 4 + 2].y, -T[2 * 4 + 2].x);
+  T[2 * 4 + 3] = c_mul(T[2 * 4 + 3], make_float2(-h, -h));
+  T[3 * 4 + 1] = c_mul(T[3 * 4 + 1], make_float2(s1, -c1));
+  T[3 * 4 + 2] = c_mul(T[3 * 4 + 2], make_float2(-h, -h));
+  T[3 * 4 + 3] = c_mul(T[3 * 4 + 3], make_float2(-c1, s1));
+#pragma unroll
+  for (int k1 = 0; k1 < 4; ++k1) {
+    float2 b0 = T[k1], b1 = T[4 + k1], b2 = T[8 + k1], b3 = T[12 + k1];
+    dft4(b0, b1, b2, b3);
+    v[k1] = b0;
+    v[k1 + 4] = b1;
+    v[k1 + 8] = b2;
+    v[k1 + 12] = b3;
+  }
+}
+
+template <int E>
+__device__ __forceinline__ void dft_small(float2* v) {
+  if constexpr (E == 2) dft2(v[0], v[1]);
+  if constexpr (E == 4) dft4(v[0], v[1], v[2], v[3]);
+  if constexpr (E == 8) dft8(v);
+  if constexpr (E == 16) dft16(v);
+}
+
+// Orders the LDS accesses of one wave (its lanes exchange data through a
+// wave-private scratch; no other wave is involved).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+}
+
+// ---------------------------------------------------------------------------
+// Wave FFT: one wave transforms one line of L = 64 E points (E = 1..16, a
+// power of two), forward and unnormalised. On entry lane q holds
+// v[e] = x[q + 64 e]. Cooley-Tukey with L = E x 64 (n = q + 64 e,
+// k = k1 + E k2): an E-point DFT over e in registers, twiddles W_L^{q k1},
+// then the 64-point DFT over q as 8 x 8 (q = 8 a + b, k2 = c + 8 d) through
+// `scr`, a wave-private LDS scratch of L values. store(k, X[k]) receives the
+// result; each store instruction of the wave covers 64 consecutive bins.
+// tw: W_L^k, k < L.
+// ---------------------------------------------------------------------------
+template <int E, class Store>
+__device__ __forceinline__ void wave_fft(float2 (&v)[E], float2* __restrict__ scr, const float2* __restrict__ tw,
+                                         Store&& store) {
+  const int lane = threadIdx.x & 63;
+  dft_small<E>(v);
+#pragma unroll
+  for (int k1 = 1; k1 < E; ++k1) v[k1] = c_mul(v[k1], tw[lane * k1]);
+#pragma unroll
+  for (int k1 = 0; k1 < E; ++k1) scr[k1 * 64 + lane] = v[k1];
+  wave_lds_sync();
+  constexpr int NJ = (8 * E + 63) / 64;
+  float2 u[NJ][8];
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) {
+    const int p = lane + 64 * j;
+    if (p < 8 * E) {
+      const int k1 = p >> 3, b = p & 7;
+#pragma unroll
+      for (int a = 0; a < 8; ++a) u[j][a] = scr[k1 * 64 + 8 * a + b];
+      dft8(u[j]);
+#pragma unroll
+      for (int c = 1; c < 8; ++c) u[j][c] = c_mul(u[j][c], tw[E * b * c]);
+    }
+  }
+  wave_lds_sync();
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) {
+    const int p = lane + 64 * j;
+    if (p < 8 * E) {
+      const int k1 = p >> 3, b = p & 7;
+#pragma unroll
+      for (int c = 0; c < 8; ++c) scr[k1 * 64 + 8 * c + b] = u[j][c];
+    }
+  }
+  wave_lds_sync();
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) {
+    const int p = lane + 64 * j;
+    if (p < 8 * E) {
+      const int k1 = p >> 3, c = p & 7;
+#pragma unroll
+      for (int b = 0; b < 8; ++b) u[j][b] = scr[k1 * 64 + 8 * c + b];
+      dft8(u[j]);
+#pragma unroll
+      for (int d = 0; d < 8; ++d) store(k1 + E * (c + 8 * d), u[j][d]);
+    }
+  }
+  wave_lds_sync();
+}
+
 // ---------------------------------------------------------------------------
 // One Stockham stage over `nl` lines: in -> out, radix R, Ns = product of
 // the radices of earlier stages. Butterfly j of a line reads in[j + q L/R]

@@ -173,9 +173,47 @@ __device__ __forceinline__ SolveLds carve_solve_lds(char* smem, int L, int rec_l
   return s;
 }
 
+// Wave path of the solve loop (L = 64 E, 64 <= L <= 512, one wave per
+// line): wave w holds line w's values at l = lane + 64 e in registers.
+constexpr int kEMax = 8;
+
+template <int D, bool kPow2>
+__device__ __forceinline__ void wave_prefetch(float2 (&pf)[kEMax], int E, const Geo<D>& g,
+                                              const float2* __restrict__ x, const int32_t* __restrict__ row,
+                                              const float2* __restrict__ pre, bool precomputed, int w) {
+  const int lane = threadIdx.x & 63;
+  const uint32_t L = g.L;
+#pragma unroll
+  for (int e = 0; e < kEMax; ++e) {
+    if (e < E) {
+      const uint32_t l = lane + 64 * e;
+      if (precomputed) {
+        pf[e] = ld_g(pre, w * L + l);
+      } else {
+        int64_t step[D];
+        const int64_t flat = line_sample<D, kPow2>(g, row, l, step);
+        int64_t off = 0;
+#pragma unroll
+        for (int k = 0; k < D; ++k)
+          if (w == k + 1) off = step[k];
+        pf[e] = ld_g(x, flat + off);
+      }
+    }
+  }
+}
+
+template <int E>
+__device__ __forceinline__ void wave_fft_to_lds(float2 (&pf)[kEMax], float scale, float2* scr, const float2* tw,
+                                                float2* dst) {
+  float2 v[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) v[e] = c_scale(pf[e], scale);
+  wave_fft<E>(v, scr, tw, [&](int k, float2 val) { dst[k] = val; });
+}
+
 // kRecLds: the record list lives in LDS and is mirrored to the outputs;
 // otherwise it is read back from the output arrays.
-template <int D, bool kPow2, bool kRecLds>
+template <int D, bool kPow2, bool kRecLds, bool kWave>
 __device__ __forceinline__ void solve_cube(const CubeDesc& cd, const float2* __restrict__ x, const OutPtrs out,
                                            const int32_t* __restrict__ sched, const float2* __restrict__ twall,
                                            const float2* __restrict__ pre, int pre_count, char* smem) {
@@ -195,9 +233,20 @@ __device__ __forceinline__ void solve_cube(const CubeDesc& cd, const float2* __r
   const float2* tw = s.tw;
   float2* oamps = (float2*)out.amps;
   const bool use_pf = L <= (uint32_t)(kPfU * B);
+  const int wv = tid >> 6;
+  const int lane = tid & 63;
+  const int E = (int)(L >> 6);
+  // The host sends a cube here only if 64 <= L <= 512 and blockDim has at
+  // least D+1 waves.
+  constexpr bool wave_path = kWave && kPow2;
 
   Prefetch<D> pf;
-  if (use_pf) prefetch_issue<D, kPow2>(pf, g, x, sch, pre, 0 < pre_count);
+  float2 pfw[kEMax];
+  if constexpr (wave_path) {
+    if (wv <= D) wave_prefetch<D, kPow2>(pfw, E, g, x, sch, pre, 0 < pre_count, wv);
+  } else if (use_pf) {
+    prefetch_issue<D, kPow2>(pf, g, x, sch, pre, 0 < pre_count);
+  }
 
   int kc = 0;
   int status = kStatusIncomplete;
@@ -205,6 +254,33 @@ __device__ __forceinline__ void solve_cube(const CubeDesc& cd, const float2* __r
   for (int t = 0; t < T; ++t) {
     const int32_t* at = sch + t * 2 * D;
     const bool precomputed = t < pre_count;
+    float2* S;
+    if constexpr (wave_path) {
+      if (wv <= D) {
+        float2 cur[kEMax];
+#pragma unroll
+        for (int e = 0; e < kEMax; ++e) cur[e] = pfw[e];
+        if (t + 1 < T)
+          wave_prefetch<D, kPow2>(pfw, E, g, x, at + 2 * D, pre + (int64_t)(t + 1) * (D + 1) * L, t + 1 < pre_count,
+                                  wv);
+        float2* dst = s.bufA + wv * L;
+        if (precomputed) {
+#pragma unroll
+          for (int e = 0; e < kEMax; ++e)
+            if (e < E) dst[lane + 64 * e] = cur[e];
+        } else {
+          float2* scr = s.bufB + wv * L;
+          switch (E) {
+            case 1: wave_fft_to_lds<1>(cur, inv_L, scr, tw, dst); break;
+            case 2: wave_fft_to_lds<2>(cur, inv_L, scr, tw, dst); break;
+            case 4: wave_fft_to_lds<4>(cur, inv_L, scr, tw, dst); break;
+            default: wave_fft_to_lds<8>(cur, inv_L, scr, tw, dst); break;
+          }
+        }
+      }
+      lds_barrier();
+      S = s.bufA;
+    } else {
     if (use_pf) {
       prefetch_store<D>(pf, L, s.bufA, precomputed ? 1.0f : inv_L);
       if (t + 1 < T)
@@ -216,7 +292,8 @@ __device__ __forceinline__ void solve_cube(const CubeDesc& cd, const float2* __r
       gather_lines<D, kPow2>(s.bufA, x, g, at, 1, inv_L);
     }
     lds_barrier();
-    float2* S = precomputed ? s.bufA : block_fft<kPow2>(s.bufA, s.bufB, D + 1, (int)L, cd.nstages, cd.radix, tw);
+    S = precomputed ? s.bufA : block_fft<kPow2>(s.bufA, s.bufB, D + 1, (int)L, cd.nstages, cd.radix, tw);
+    }
     uint32_t al[D], ta[D];
 #pragma unroll
     for (int k = 0; k < D; ++k) {
@@ -339,19 +416,23 @@ __device__ __forceinline__ void solve_cube(const CubeDesc& cd, const float2* __r
   __syncthreads();
 }
 
-template <int D, bool kPow2, bool kRecLds>
-__global__ void k_solve_plain(const CubeDesc* __restrict__ descs, int cube, const float2* __restrict__ x,
+// Solve kernels run 64..512 threads per work-group; the register budget is
+// set for three waves per SIMD.
+#define FPS_SOLVE_ATTRS __attribute__((amdgpu_flat_work_group_size(64, 512), amdgpu_waves_per_eu(3)))
+
+template <int D, bool kPow2, bool kRecLds, bool kWave>
+__global__ FPS_SOLVE_ATTRS void k_solve_plain(const CubeDesc* __restrict__ descs, int cube, const float2* __restrict__ x,
                               OutPtrs out, const int32_t* __restrict__ sched, const float2* __restrict__ tw,
                               const float2* __restrict__ pre, int pre_count) {
   extern __shared__ char lds_solve[];
-  solve_cube<D, kPow2, kRecLds>(descs[cube], x, out, sched, tw, pre, pre_count, lds_solve);
+  solve_cube<D, kPow2, kRecLds, kWave>(descs[cube], x, out, sched, tw, pre, pre_count, lds_solve);
 }
 
 // Persistent: every work-group loops taking the next cube of `order` from
 // the queue counter; it leaves when the counter passes the cube count, so
 // every wave reaches the exit.
-template <int D, bool kPow2, bool kRecLds>
-__global__ void k_solve_batched(const CubeDesc* __restrict__ descs, const float2* const* __restrict__ xs,
+template <int D, bool kPow2, bool kRecLds, bool kWave>
+__global__ FPS_SOLVE_ATTRS void k_solve_batched(const CubeDesc* __restrict__ descs, const float2* const* __restrict__ xs,
                                 const OutPtrs* __restrict__ outs, const int32_t* __restrict__ sched,
                                 const float2* __restrict__ tw, const int32_t* __restrict__ order, int ncubes,
                                 int* __restrict__ queue) {
@@ -365,7 +446,7 @@ __global__ void k_solve_batched(const CubeDesc* __restrict__ descs, const float2
     __syncthreads();
     if (idx >= ncubes) break;
     const int c = __builtin_amdgcn_readfirstlane(order[idx]);
-    solve_cube<D, kPow2, kRecLds>(descs[c], xs[c], outs[c], sched, tw, nullptr, 0, lds_solve);
+    solve_cube<D, kPow2, kRecLds, kWave>(descs[c], xs[c], outs[c], sched, tw, nullptr, 0, lds_solve);
   }
 }
 
@@ -527,16 +608,33 @@ __global__ void k_backward(const CubeDesc* __restrict__ descs, int cube, OutPtrs
     __VA_ARGS__;                        \
   }
 
+// Solve kernels: the wave path exists only for power-of-two lines.
+#define FPS_DISPATCH_SOLVE(key, ...)                                                          \
+  FPS_DISPATCH_D(key.D, FPS_DISPATCH_B(key.rec_lds, kR, {                                     \
+    if (key.pow2 && key.wave) {                                                               \
+      constexpr bool kP = true, kW = true;                                                    \
+      __VA_ARGS__;                                                                            \
+    } else if (key.pow2) {                                                                    \
+      constexpr bool kP = true, kW = false;                                                   \
+      __VA_ARGS__;                                                                            \
+    } else {                                                                                  \
+      constexpr bool kP = false, kW = false;                                                  \
+      __VA_ARGS__;                                                                            \
+    }                                                                                         \
+  }))
+
 const void* kernel_ptr(KernelKind kind, const KernelKey& key) {
   const void* fn = nullptr;
-  FPS_DISPATCH_D(key.D, FPS_DISPATCH_B(key.pow2, kP, FPS_DISPATCH_B(key.rec_lds, kR, {
-    switch (kind) {
-      case KernelKind::kLines: fn = (const void*)k_lines<kD, kP>; break;
-      case KernelKind::kSolvePlain: fn = (const void*)k_solve_plain<kD, kP, kR>; break;
-      case KernelKind::kSolveBatched: fn = (const void*)k_solve_batched<kD, kP, kR>; break;
-      case KernelKind::kBackward: fn = (const void*)k_backward<kD, kP>; break;
-    }
-  })))
+  if (kind == KernelKind::kSolvePlain || kind == KernelKind::kSolveBatched) {
+    FPS_DISPATCH_SOLVE(key, {
+      fn = kind == KernelKind::kSolvePlain ? (const void*)k_solve_plain<kD, kP, kR, kW>
+                                           : (const void*)k_solve_batched<kD, kP, kR, kW>;
+    })
+    return fn;
+  }
+  FPS_DISPATCH_D(key.D, FPS_DISPATCH_B(key.pow2, kP, {
+    fn = kind == KernelKind::kLines ? (const void*)k_lines<kD, kP> : (const void*)k_backward<kD, kP>;
+  }))
   return fn;
 }
 
@@ -563,10 +661,10 @@ hipError_t launch_lines_items(const LaunchCtx& ctx, const KernelKey& key, const 
 hipError_t launch_solve_plain(const LaunchCtx& ctx, const KernelKey& key, int cube, const float2* x,
                               const OutPtrs& out, const float2* pre, int pre_count, size_t lds, int threads,
                               hipStream_t st) {
-  FPS_DISPATCH_D(key.D, FPS_DISPATCH_B(key.pow2, kP, FPS_DISPATCH_B(key.rec_lds, kR, {
-    hipLaunchKernelGGL((k_solve_plain<kD, kP, kR>), dim3(1), dim3(threads), lds, st, ctx.descs, cube, x, out,
+  FPS_DISPATCH_SOLVE(key, {
+    hipLaunchKernelGGL((k_solve_plain<kD, kP, kR, kW>), dim3(1), dim3(threads), lds, st, ctx.descs, cube, x, out,
                        ctx.sched, ctx.tw, pre, pre_count);
-  })))
+  })
   return hipGetLastError();
 }
 
@@ -578,10 +676,10 @@ hipError_t launch_reset(int* p, int n, hipStream_t st) {
 hipError_t launch_solve_batched(const LaunchCtx& ctx, const KernelKey& key, const float2* const* xs,
                                 const OutPtrs* outs, const int32_t* order, int ncubes, int* queue, int grid,
                                 size_t lds, int threads, hipStream_t st) {
-  FPS_DISPATCH_D(key.D, FPS_DISPATCH_B(key.pow2, kP, FPS_DISPATCH_B(key.rec_lds, kR, {
-    hipLaunchKernelGGL((k_solve_batched<kD, kP, kR>), dim3(grid), dim3(threads), lds, st, ctx.descs, xs, outs,
+  FPS_DISPATCH_SOLVE(key, {
+    hipLaunchKernelGGL((k_solve_batched<kD, kP, kR, kW>), dim3(grid), dim3(threads), lds, st, ctx.descs, xs, outs,
                        ctx.sched, ctx.tw, order, ncubes, queue);
-  })))
+  })
   return hipGetLastError();
 }
 

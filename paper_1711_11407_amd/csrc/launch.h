@@ -20,7 +20,10 @@ struct KernelKey {
   int D;
   bool pow2;
   bool rec_lds;
-  bool operator==(const KernelKey& o) const { return D == o.D && pow2 == o.pow2 && rec_lds == o.rec_lds; }
+  bool wave;  // solve kernels: one wave per line (64 <= L <= 512, >= D+1 waves)
+  bool operator==(const KernelKey& o) const {
+    return D == o.D && pow2 == o.pow2 && rec_lds == o.rec_lds && wave == o.wave;
+  }
 };
 
 enum class KernelKind { kLines, kSolvePlain, kSolveBatched, kBackward };

@@ -278,7 +278,9 @@ size_t lines_single_lds_bytes(const CubeDesc& c) { return lines_lds_bytes(c.D, c
 
 fpssft::KernelKey key_of(const fpssft_plan_t p, int c) {
   const CubeDesc& cd = p->descs[c];
-  return fpssft::KernelKey{cd.D, cd.Lmask >= 0, p->rec_lds};
+  const bool pow2 = cd.Lmask >= 0;
+  const bool wave = pow2 && cd.L >= 64 && cd.L <= 512 && p->tune.block_threads / 64 >= cd.D + 1;
+  return fpssft::KernelKey{cd.D, pow2, p->rec_lds, wave};
 }
 
 void destroy_plan(fpssft_plan_t p) {
@@ -324,7 +326,7 @@ fpssft_status build_plan(const fpssft_desc* descs, int32_t batch, const fpssft_t
     if (tuning->lines_wg) tn.lines_wg = tuning->lines_wg;
     if (tuning->lines_threads) tn.lines_threads = tuning->lines_threads;
   }
-  if (tn.block_threads < 64 || tn.block_threads > 1024 || tn.block_threads % 64) return FPSSFT_ERR_INVALID_ARG;
+  if (tn.block_threads < 64 || tn.block_threads > 512 || tn.block_threads % 64) return FPSSFT_ERR_INVALID_ARG;
   if (tn.lines_threads < 64 || tn.lines_threads > 1024 || tn.lines_threads % 64) return FPSSFT_ERR_INVALID_ARG;
   if (tn.max_radix != 2 && tn.max_radix != 4 && tn.max_radix != 8) return FPSSFT_ERR_INVALID_ARG;
   if (tn.lines_wg < 1) return FPSSFT_ERR_INVALID_ARG;

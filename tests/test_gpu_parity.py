@@ -68,7 +68,7 @@ def test_plain_shapes(F, dims, K, T):
 
 
 @pytest.mark.parametrize("tuning", [
-    dict(block_threads=64), dict(block_threads=1024), dict(max_radix=2), dict(max_radix=4),
+    dict(block_threads=64), dict(block_threads=512), dict(block_threads=128), dict(max_radix=2), dict(max_radix=4),
     dict(chunk_iters=0), dict(chunk_iters=1), dict(chunk_iters=64), dict(lines_wg=3),
     dict(lines_wg=64, block_threads=512),
 ])
@@ -181,3 +181,21 @@ def test_noisy_cfg2_reports_agreement(F):
     log(f"cfg2: gpu k={got['k']} iters={got['iters']} recall={len(g & truth)/len(truth):.2f} "
         f"oracle k={ref.k} recall={len(o & truth)/len(truth):.2f} jaccard(gpu,oracle)="
         f"{len(g & o)/max(1, len(g | o)):.2f}")
+
+
+def test_lines_fft_all_mixed_lengths_matches_single(F):
+    """The persistent whole-budget line FFT over a group of cubes of mixed
+    line lengths (and a 3-D group): every packed block equals the
+    single-cube line FFT of the same iterations."""
+    torch, dev = torch_dev()
+    shapes = [(64, 64), (128, 64), (512, 512), (64, 512), (256, 256), (128, 128, 128), (64, 128, 64)]
+    T = [21, 21, 40, 21, 85, 30, 12]
+    specs = [spec_for(F, d, 50 + i, max_iters=T[i]) for i, d in enumerate(shapes)]
+    plan = F.Plan(specs)
+    xs = [torch.from_numpy(W.random_dense(d, 60 + i).astype(np.complex64)).to(dev) for i, d in enumerate(shapes)]
+    allsp = plan.lines_fft_all(xs).cpu().numpy()
+    for c, d in enumerate(shapes):
+        L, Tc, off = plan.info[c]
+        blk = allsp[off:off + Tc * (len(d) + 1) * L].reshape(Tc, len(d) + 1, L)
+        one = plan.lines_fft(c, xs[c], 0, Tc).cpu().numpy()
+        np.testing.assert_allclose(blk, one, rtol=0, atol=1e-6 * np.abs(one).max())
