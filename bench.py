@@ -130,6 +130,53 @@ def event_time_ms(torch, fn, reps):
     return e0.elapsed_time(e1) / reps
 
 
+def summarize_counters(dirs):
+    """profiles/traffic.json from four rocprofv3 --pmc output directories:
+    FETCH_SIZE and WRITE_SIZE of a `--only lines` or `--only batched` run, and
+    the same two counters of `--only copy` (a 1 GiB device copy: 1 GiB read,
+    1 GiB written) that scale the counters to bytes."""
+    import csv
+    fetch_dir, write_dir, cfetch_dir, cwrite_dir = dirs
+
+    def per_kernel(d, counter):
+        vals = {}
+        for r in csv.DictReader(open(os.path.join(d, "run_counter_collection.csv"))):
+            if r["Counter_Name"] != counter:
+                continue
+            vals.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+        return vals
+
+    gib = float(1 << 30)
+    cf = [v for k, vs in per_kernel(cfetch_dir, "FETCH_SIZE").items() if "copyBuffer" in k for v in vs]
+    cw = [v for k, vs in per_kernel(cwrite_dir, "WRITE_SIZE").items() if "copyBuffer" in k for v in vs]
+    f_scale = gib / (1024.0 * (sum(cf) / len(cf)))
+    w_scale = gib / (1024.0 * (sum(cw) / len(cw)))
+    out = {"kernel_source_hash": kernel_source_hash(), "fetch_scale": f_scale, "write_scale": w_scale,
+           "kernels": {}}
+    try:
+        with open(TRAFFIC_FILE) as f:
+            old = json.load(f)
+        if old.get("kernel_source_hash") == out["kernel_source_hash"]:
+            out["kernels"] = old.get("kernels", {})
+    except FileNotFoundError:
+        pass
+    fv, wv = per_kernel(fetch_dir, "FETCH_SIZE"), per_kernel(write_dir, "WRITE_SIZE")
+    for name in fv:
+        short = next((k for k in ("k_solve_batched", "k_lines", "k_solve_plain", "k_backward")
+                      if "fpssft::" + k in name), None)
+        if short is None or name not in wv:
+            continue
+        # the largest dispatches are the timed launches of the workload
+        fb = max(fv[name]) * 1024.0 * f_scale
+        wb = max(wv[name]) * 1024.0 * w_scale
+        out["kernels"][short] = {"fetch_bytes": fb, "write_bytes": wb, "hbm_bytes_per_dispatch": fb + wb,
+                                 "kernel_name": name}
+    os.makedirs(os.path.dirname(TRAFFIC_FILE), exist_ok=True)
+    with open(TRAFFIC_FILE, "w") as f:
+        json.dump(out, f, indent=1, sort_keys=True)
+    print(json.dumps(out, indent=1))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -137,7 +184,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--only", choices=["copy", "lines", "batched", "plain"], default=None)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--traffic-from", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
+                    help="write profiles/traffic.json from rocprofv3 --pmc output directories")
     args = ap.parse_args()
+    if args.traffic_from:
+        summarize_counters(args.traffic_from)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU only: independent cubes shard across "
                                    "GPUs with no exchange, and no multi-GPU path is built"}))
