@@ -200,19 +200,35 @@ __device__ __forceinline__ void wave_lds_sync() {
 // v[e] = x[q + 64 e]. Cooley-Tukey with L = E x 64 (n = q + 64 e,
 // k = k1 + E k2): an E-point DFT over e in registers, twiddles W_L^{q k1},
 // then the 64-point DFT over q as 8 x 8 (q = 8 a + b, k2 = c + 8 d) through
-// `scr`, a wave-private LDS scratch of L values. store(k, X[k]) receives the
-// result; each store instruction of the wave covers 64 consecutive bins.
-// tw: W_L^k, k < L.
+// `scr`, a wave-private LDS scratch of 72 E values (wave_scratch_elems).
+// store(k, X[k]) receives the result; each store instruction of the wave
+// covers 64 consecutive bins. tw: W_L^k, k < L.
+//
+// Scratch layout: row k1 holds q = 8 x + y at wave_slot = 72 k1 + 9 x + y.
+// Every access of the 8 x 8 steps is then a per-lane base plus an immediate
+// offset, and none meets more than a 2-way LDS bank conflict (64-wide rows
+// reach 8-way on the transposed reads). Each stage's twiddle reads are
+// issued together, ahead of the arithmetic that uses them.
 // ---------------------------------------------------------------------------
+__host__ __device__ constexpr int wave_scratch_elems(int L) { return L + L / 8; }
+
+__device__ __forceinline__ int wave_slot(int k1, int q) { return k1 * 72 + 9 * (q >> 3) + (q & 7); }
+
 template <int E, class Store>
 __device__ __forceinline__ void wave_fft(float2 (&v)[E], float2* __restrict__ scr, const float2* __restrict__ tw,
                                          Store&& store) {
   const int lane = threadIdx.x & 63;
   dft_small<E>(v);
+  if constexpr (E > 1) {
+    float2 w[E];
 #pragma unroll
-  for (int k1 = 1; k1 < E; ++k1) v[k1] = c_mul(v[k1], tw[lane * k1]);
+    for (int k1 = 1; k1 < E; ++k1) w[k1] = tw[lane * k1];
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-  for (int k1 = 0; k1 < E; ++k1) scr[k1 * 64 + lane] = v[k1];
+    for (int k1 = 1; k1 < E; ++k1) v[k1] = c_mul(v[k1], w[k1]);
+  }
+#pragma unroll
+  for (int k1 = 0; k1 < E; ++k1) scr[wave_slot(k1, lane)] = v[k1];
   wave_lds_sync();
   constexpr int NJ = (8 * E + 63) / 64;
   float2 u[NJ][8];
@@ -221,11 +237,15 @@ __device__ __forceinline__ void wave_fft(float2 (&v)[E], float2* __restrict__ sc
     const int p = lane + 64 * j;
     if (p < 8 * E) {
       const int k1 = p >> 3, b = p & 7;
+      float2 w[8];
 #pragma unroll
-      for (int a = 0; a < 8; ++a) u[j][a] = scr[k1 * 64 + 8 * a + b];
+      for (int a = 0; a < 8; ++a) u[j][a] = scr[wave_slot(k1, 8 * a + b)];
+#pragma unroll
+      for (int c = 1; c < 8; ++c) w[c] = tw[E * b * c];
+      __builtin_amdgcn_sched_barrier(0);
       dft8(u[j]);
 #pragma unroll
-      for (int c = 1; c < 8; ++c) u[j][c] = c_mul(u[j][c], tw[E * b * c]);
+      for (int c = 1; c < 8; ++c) u[j][c] = c_mul(u[j][c], w[c]);
     }
   }
   wave_lds_sync();
@@ -235,7 +255,7 @@ __device__ __forceinline__ void wave_fft(float2 (&v)[E], float2* __restrict__ sc
     if (p < 8 * E) {
       const int k1 = p >> 3, b = p & 7;
 #pragma unroll
-      for (int c = 0; c < 8; ++c) scr[k1 * 64 + 8 * c + b] = u[j][c];
+      for (int c = 0; c < 8; ++c) scr[wave_slot(k1, 8 * c + b)] = u[j][c];
     }
   }
   wave_lds_sync();
@@ -245,7 +265,7 @@ __device__ __forceinline__ void wave_fft(float2 (&v)[E], float2* __restrict__ sc
     if (p < 8 * E) {
       const int k1 = p >> 3, c = p & 7;
 #pragma unroll
-      for (int b = 0; b < 8; ++b) u[j][b] = scr[k1 * 64 + 8 * c + b];
+      for (int b = 0; b < 8; ++b) u[j][b] = scr[wave_slot(k1, 8 * c + b)];
       dft8(u[j]);
 #pragma unroll
       for (int d = 0; d < 8; ++d) store(k1 + E * (c + 8 * d), u[j][d]);

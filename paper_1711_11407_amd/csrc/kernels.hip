@@ -100,12 +100,14 @@ __device__ __forceinline__ void lines_item(const CubeDesc& cd, const float2* __r
   for (int i = 0; i < tc; ++i) {
     if (use_pf) {
       prefetch_store<D>(pf, L, bufA, cd.inv_L);
-      if (i + 1 < tc) prefetch_issue<D, kPow2>(pf, g, x, sch + (i + 1) * 2 * D, nullptr, false);
     } else {
       gather_lines<D, kPow2>(bufA, x, g, sch + i * 2 * D, 1, cd.inv_L);
     }
     lds_barrier();
     const float2* S = block_fft<kPow2>(bufA, bufB, D + 1, (int)L, cd.nstages, cd.radix, tw);
+    // Next iteration's gathers go out after the transform (scattered loads in
+    // flight slow the LDS traffic of the butterflies).
+    if (use_pf && i + 1 < tc) prefetch_issue<D, kPow2>(pf, g, x, sch + (i + 1) * 2 * D, nullptr, false);
     float2* o = out + (int64_t)i * (D + 1) * L;
     for (uint32_t e = threadIdx.x; e < (D + 1) * L; e += B) st_g(o, e, S[e]);
     lds_barrier();
@@ -166,7 +168,8 @@ __device__ __forceinline__ SolveLds carve_solve_lds(char* smem, int L, int rec_l
   SolveLds s;
   s.bufA = (float2*)smem;
   s.bufB = s.bufA + (D + 1) * L;
-  s.tw = s.bufB + (D + 1) * L;
+  // bufB: the block FFT's second buffer, or the wave FFTs' scratch
+  s.tw = s.bufB + wave_scratch_elems((D + 1) * L);
   s.rec_a = s.tw + L;
   s.rec_f = (int32_t*)(s.rec_a + rec_lds);
   s.wsum = s.rec_f + rec_lds * D;
@@ -183,31 +186,40 @@ __device__ __forceinline__ void wave_prefetch(float2 (&pf)[kEMax], int E, const 
                                               const float2* __restrict__ pre, bool precomputed, int w) {
   const int lane = threadIdx.x & 63;
   const uint32_t L = g.L;
+  if (precomputed) {
+#pragma unroll
+    for (int e = 0; e < kEMax; ++e)
+      if (e < E) pf[e] = ld_g(pre, w * L + lane + 64 * e);
+    return;
+  }
+  // Line w has offsets tau + e_{w-1} (line 0: tau); slope and offsets are
+  // read once, uniform across the wave. alpha_k l + tau_k + 1 < N_k L + N_k
+  // stays below 2^32 (the plan checks N_k L < 2^31).
+  const int ws = __builtin_amdgcn_readfirstlane(w);
+  uint32_t al[D], ta[D];
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    al[k] = (uint32_t)__builtin_amdgcn_readfirstlane(row[k]);
+    ta[k] = (uint32_t)__builtin_amdgcn_readfirstlane(row[D + k]) + (k + 1 == ws ? 1u : 0u);
+  }
 #pragma unroll
   for (int e = 0; e < kEMax; ++e) {
     if (e < E) {
       const uint32_t l = lane + 64 * e;
-      if (precomputed) {
-        pf[e] = ld_g(pre, w * L + l);
-      } else {
-        int64_t step[D];
-        const int64_t flat = line_sample<D, kPow2>(g, row, l, step);
-        int64_t off = 0;
+      int64_t flat = 0;
 #pragma unroll
-        for (int k = 0; k < D; ++k)
-          if (w == k + 1) off = step[k];
-        pf[e] = ld_g(x, flat + off);
-      }
+      for (int k = 0; k < D; ++k) flat += (int64_t)umod<kPow2>(al[k] * l + ta[k], g.dims[k]) * g.stride[k];
+      pf[e] = ld_g(x, flat);
     }
   }
 }
 
 template <int E>
-__device__ __forceinline__ void wave_fft_to_lds(float2 (&pf)[kEMax], float scale, float2* scr, const float2* tw,
+__device__ __forceinline__ void wave_fft_to_lds(const float2 (&in)[kEMax], float2* scr, const float2* tw,
                                                 float2* dst) {
   float2 v[E];
 #pragma unroll
-  for (int e = 0; e < E; ++e) v[e] = c_scale(pf[e], scale);
+  for (int e = 0; e < E; ++e) v[e] = in[e];
   wave_fft<E>(v, scr, tw, [&](int k, float2 val) { dst[k] = val; });
 }
 
@@ -244,6 +256,8 @@ __device__ __forceinline__ void solve_cube(const CubeDesc& cd, const float2* __r
   float2 pfw[kEMax];
   if constexpr (wave_path) {
     if (wv <= D) wave_prefetch<D, kPow2>(pfw, E, g, x, sch, pre, 0 < pre_count, wv);
+    // The wave transforms read twiddles that other threads staged above.
+    lds_barrier();
   } else if (use_pf) {
     prefetch_issue<D, kPow2>(pf, g, x, sch, pre, 0 < pre_count);
   }
@@ -257,34 +271,43 @@ __device__ __forceinline__ void solve_cube(const CubeDesc& cd, const float2* __r
     float2* S;
     if constexpr (wave_path) {
       if (wv <= D) {
+        // Consume the prefetched samples first, so that the registers they
+        // occupy are free when the next iteration's loads are issued into
+        // them; otherwise the compiler carries the new loads through a
+        // register copy that waits for them right after the transform.
+        const float sc = precomputed ? 1.0f : inv_L;
         float2 cur[kEMax];
 #pragma unroll
-        for (int e = 0; e < kEMax; ++e) cur[e] = pfw[e];
-        if (t + 1 < T)
-          wave_prefetch<D, kPow2>(pfw, E, g, x, at + 2 * D, pre + (int64_t)(t + 1) * (D + 1) * L, t + 1 < pre_count,
-                                  wv);
+        for (int e = 0; e < kEMax; ++e) {
+          cur[e] = c_scale(pfw[e], sc);
+          __asm__ volatile("" : "+v"(cur[e].x), "+v"(cur[e].y));
+        }
         float2* dst = s.bufA + wv * L;
         if (precomputed) {
 #pragma unroll
           for (int e = 0; e < kEMax; ++e)
             if (e < E) dst[lane + 64 * e] = cur[e];
         } else {
-          float2* scr = s.bufB + wv * L;
+          float2* scr = s.bufB + wv * wave_scratch_elems((int)L);
           switch (E) {
-            case 1: wave_fft_to_lds<1>(cur, inv_L, scr, tw, dst); break;
-            case 2: wave_fft_to_lds<2>(cur, inv_L, scr, tw, dst); break;
-            case 4: wave_fft_to_lds<4>(cur, inv_L, scr, tw, dst); break;
-            default: wave_fft_to_lds<8>(cur, inv_L, scr, tw, dst); break;
+            case 1: wave_fft_to_lds<1>(cur, scr, tw, dst); break;
+            case 2: wave_fft_to_lds<2>(cur, scr, tw, dst); break;
+            case 4: wave_fft_to_lds<4>(cur, scr, tw, dst); break;
+            default: wave_fft_to_lds<8>(cur, scr, tw, dst); break;
           }
         }
+        // The next iteration's gathers are issued after the transform: in
+        // flight, scattered loads slow this wave's LDS traffic several-fold;
+        // they overlap the peel and the decode instead.
+        if (t + 1 < T)
+          wave_prefetch<D, kPow2>(pfw, E, g, x, at + 2 * D, pre + (int64_t)(t + 1) * (D + 1) * L, t + 1 < pre_count,
+                                  wv);
       }
       lds_barrier();
       S = s.bufA;
     } else {
     if (use_pf) {
       prefetch_store<D>(pf, L, s.bufA, precomputed ? 1.0f : inv_L);
-      if (t + 1 < T)
-        prefetch_issue<D, kPow2>(pf, g, x, at + 2 * D, pre + (int64_t)(t + 1) * (D + 1) * L, t + 1 < pre_count);
     } else if (precomputed) {
       const float2* src = pre + (int64_t)t * (D + 1) * L;
       for (uint32_t e = tid; e < (D + 1) * L; e += B) s.bufA[e] = ld_g(src, e);
@@ -293,6 +316,8 @@ __device__ __forceinline__ void solve_cube(const CubeDesc& cd, const float2* __r
     }
     lds_barrier();
     S = precomputed ? s.bufA : block_fft<kPow2>(s.bufA, s.bufB, D + 1, (int)L, cd.nstages, cd.radix, tw);
+    if (use_pf && t + 1 < T)
+      prefetch_issue<D, kPow2>(pf, g, x, at + 2 * D, pre + (int64_t)(t + 1) * (D + 1) * L, t + 1 < pre_count);
     }
     uint32_t al[D], ta[D];
 #pragma unroll
@@ -418,13 +443,13 @@ __device__ __forceinline__ void solve_cube(const CubeDesc& cd, const float2* __r
 
 // Solve kernels run 64..512 threads per work-group; the register budget is
 // set for three waves per SIMD.
-#define FPS_SOLVE_ATTRS __attribute__((amdgpu_flat_work_group_size(64, 512), amdgpu_waves_per_eu(3)))
+#define FPS_SOLVE_ATTRS __attribute__((amdgpu_flat_work_group_size(64, 512), amdgpu_waves_per_eu(3, 3)))
 
 template <int D, bool kPow2, bool kRecLds, bool kWave>
 __global__ FPS_SOLVE_ATTRS void k_solve_plain(const CubeDesc* __restrict__ descs, int cube, const float2* __restrict__ x,
                               OutPtrs out, const int32_t* __restrict__ sched, const float2* __restrict__ tw,
                               const float2* __restrict__ pre, int pre_count) {
-  extern __shared__ char lds_solve[];
+  extern __shared__ __attribute__((aligned(16))) char lds_solve[];
   solve_cube<D, kPow2, kRecLds, kWave>(descs[cube], x, out, sched, tw, pre, pre_count, lds_solve);
 }
 
@@ -436,7 +461,7 @@ __global__ FPS_SOLVE_ATTRS void k_solve_batched(const CubeDesc* __restrict__ des
                                 const OutPtrs* __restrict__ outs, const int32_t* __restrict__ sched,
                                 const float2* __restrict__ tw, const int32_t* __restrict__ order, int ncubes,
                                 int* __restrict__ queue) {
-  extern __shared__ char lds_solve[];
+  extern __shared__ __attribute__((aligned(16))) char lds_solve[];
   __shared__ int s_idx;
   for (;;) {
     if (threadIdx.x == 0) s_idx = atomicAdd(queue, 1);
@@ -563,7 +588,7 @@ __global__ void k_backward(const CubeDesc* __restrict__ descs, int cube, OutPtrs
                            const int32_t* __restrict__ order, const OutPtrs* __restrict__ fwds,
                            const float2* const* __restrict__ gas, float2* const* __restrict__ gxs,
                            const int32_t* __restrict__ sched, const float2* __restrict__ tw) {
-  extern __shared__ char lds_bwd[];
+  extern __shared__ __attribute__((aligned(16))) char lds_bwd[];
   if (cube >= 0) {
     backward_cube<D, kPow2>(descs[cube], fwd_single, ga_single, gx_single, sched, tw, lds_bwd);
   } else {

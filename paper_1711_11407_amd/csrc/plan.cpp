@@ -261,7 +261,9 @@ struct fpssft_plan_st {
 namespace {
 
 size_t solve_lds_bytes(const CubeDesc& c, int rec_lds) {
-  size_t b = (2 * (size_t)(c.D + 1) + 1) * c.L * sizeof(float2);
+  // line buffer, second buffer / wave-FFT scratch (9/8 of the lines), twiddles
+  const size_t lines = (size_t)(c.D + 1) * c.L;
+  size_t b = (2 * lines + lines / 8 + c.L) * sizeof(float2);
   b += (size_t)rec_lds * sizeof(float2) + (size_t)rec_lds * c.D * sizeof(int32_t);
   b += 64 * sizeof(int);
   return b;
