@@ -202,7 +202,9 @@ __device__ __forceinline__ void wave_lds_sync() {
 // then the 64-point DFT over q as 8 x 8 (q = 8 a + b, k2 = c + 8 d) through
 // `scr`, a wave-private LDS scratch of 72 E values (wave_scratch_elems).
 // store(k, X[k]) receives the result; each store instruction of the wave
-// covers 64 consecutive bins. tw: W_L^k, k < L.
+// covers 64 consecutive bins. tw: W_L^k, k < L. For E <= 8 every scratch
+// read of the wave precedes every result store, so the result may overwrite
+// the scratch (scr is not restrict-qualified for that reason).
 //
 // Scratch layout: row k1 holds q = 8 x + y at wave_slot = 72 k1 + 9 x + y.
 // Every access of the 8 x 8 steps is then a per-lane base plus an immediate
@@ -215,8 +217,7 @@ __host__ __device__ constexpr int wave_scratch_elems(int L) { return L + L / 8; 
 __device__ __forceinline__ int wave_slot(int k1, int q) { return k1 * 72 + 9 * (q >> 3) + (q & 7); }
 
 template <int E, class Store>
-__device__ __forceinline__ void wave_fft(float2 (&v)[E], float2* __restrict__ scr, const float2* __restrict__ tw,
-                                         Store&& store) {
+__device__ __forceinline__ void wave_fft(float2 (&v)[E], float2* scr, const float2* __restrict__ tw, Store&& store) {
   const int lane = threadIdx.x & 63;
   dft_small<E>(v);
   if constexpr (E > 1) {

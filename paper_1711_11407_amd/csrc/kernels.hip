@@ -155,24 +155,43 @@ __global__ void k_lines(const CubeDesc* __restrict__ descs, const LineItem* __re
 // One cube, one work-group.
 // ---------------------------------------------------------------------------
 struct SolveLds {
-  float2* bufA;
-  float2* bufB;
+  float2* bufA;    // lines; on the wave path each line's row is padded
+  float2* bufB;    // the block FFT's second buffer (block path)
+  float2* P;       // [(D+1) L] peel accumulator (wave path)
   float2* tw;      // [L] twiddles W_L^k
   float2* rec_a;   // [rec_lds] amplitudes
   int32_t* rec_f;  // [rec_lds][D] frequency indices
-  int* wsum;       // [16]
+  int32_t* rec_p;  // [rec_lds] canonical position in the outputs
+  int32_t* rec_t;  // [rec_lds] iteration
+  int32_t* rec_m;  // [rec_lds] bin
+  int* wsum;       // [2][16] per-wave exchange words, double-buffered
+  int* cnt;        // [1] length of the LDS record list
 };
 
-template <int D>
+// Both layouts take 2 (D+1) L + (D+1) L / 8 + L values before the records:
+// the wave path keeps each line in a row of wave_scratch_elems(L) (its FFT
+// runs in place there) followed by the peel accumulator, the block path two
+// line buffers.
+template <int D, bool kWave>
 __device__ __forceinline__ SolveLds carve_solve_lds(char* smem, int L, int rec_lds) {
   SolveLds s;
   s.bufA = (float2*)smem;
-  s.bufB = s.bufA + (D + 1) * L;
-  // bufB: the block FFT's second buffer, or the wave FFTs' scratch
-  s.tw = s.bufB + wave_scratch_elems((D + 1) * L);
+  if constexpr (kWave) {
+    s.bufB = nullptr;
+    s.P = s.bufA + (D + 1) * wave_scratch_elems(L);
+    s.tw = s.P + (D + 1) * L;
+  } else {
+    s.bufB = s.bufA + (D + 1) * L;
+    s.P = nullptr;
+    s.tw = s.bufB + wave_scratch_elems((D + 1) * L);
+  }
   s.rec_a = s.tw + L;
   s.rec_f = (int32_t*)(s.rec_a + rec_lds);
-  s.wsum = s.rec_f + rec_lds * D;
+  s.rec_p = s.rec_f + rec_lds * D;
+  s.rec_t = s.rec_p + rec_lds;
+  s.rec_m = s.rec_t + rec_lds;
+  s.wsum = s.rec_m + rec_lds;
+  s.cnt = s.wsum + 32;
   return s;
 }
 
@@ -217,14 +236,61 @@ __device__ __forceinline__ void wave_prefetch(float2 (&pf)[kEMax], int E, const 
 template <int E>
 __device__ __forceinline__ void wave_fft_to_lds(const float2 (&in)[kEMax], float2* scr, const float2* tw,
                                                 float2* dst) {
+  // dst may be scr (in place), which needs one 8 x 8 block per lane
+  static_assert(E <= 8, "in-place wave FFT needs L <= 512");
   float2 v[E];
 #pragma unroll
   for (int e = 0; e < E; ++e) v[e] = in[e];
   wave_fft<E>(v, scr, tw, [&](int k, float2 val) { dst[k] = val; });
 }
 
-// kRecLds: the record list lives in LDS and is mirrored to the outputs;
-// otherwise it is read back from the output arrays.
+// Peel (construction-subtraction, Sec. 2.2): the projection of record j
+// onto bin b = [sum_k alpha_k c_k m_k]_L of line i is a_j e^{+j 2 pi p_i / L}
+// with p_i = [sum_k tau_k^{(i)} c_k m_k]_L (Eq. freqSum, Eq. orthogonality).
+// Records j = j0, j0 + js, ... < kc are accumulated into acc (lines astr
+// apart) with the given sign (LDS atomics: several records can share a bin).
+template <int D, bool kPow2, bool kRecLds>
+__device__ __forceinline__ void peel_records(const Geo<D>& g, const uint32_t (&al)[D], const uint32_t (&ta)[D],
+                                             const SolveLds& s, const OutPtrs& out, const float2* tw, int j0,
+                                             int js, int kc, float2* acc, int astr, float sign) {
+  const uint32_t L = g.L;
+  const float2* oamps = (const float2*)out.amps;
+  for (int j = j0; j < kc; j += js) {
+    uint32_t gk[D];
+    uint32_t b = 0, p0 = 0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      const int32_t f = kRecLds ? s.rec_f[j * D + k] : ld_gi(out.freqs, j * D + k);
+      gk[k] = g.c[k] * (uint32_t)f;
+      b = umod<kPow2>(b + al[k] * gk[k], L);
+      p0 = umod<kPow2>(p0 + ta[k] * gk[k], L);
+    }
+    const float2 a = kRecLds ? s.rec_a[j] : ld_g(oamps, j);
+    float2 c = c_mulc(a, tw[p0]);
+    atomicAdd(&acc[b].x, sign * c.x);
+    atomicAdd(&acc[b].y, sign * c.y);
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      uint32_t p = p0 + gk[k];
+      if (p >= L) p -= L;
+      c = c_mulc(a, tw[p]);
+      atomicAdd(&acc[(k + 1) * astr + b].x, sign * c.x);
+      atomicAdd(&acc[(k + 1) * astr + b].y, sign * c.y);
+    }
+  }
+}
+
+// kRecLds: the record list lives in LDS (in the order the work-group's waves
+// appended it, which the peel does not depend on) and is written to the
+// outputs in canonical order; otherwise the peel reads the outputs.
+//
+// One iteration (wave path, more waves than lines): waves 0..D transform
+// their line into bufA while the remaining waves peel the records found so
+// far into P; one barrier; every bin is tested and decoded from bufA - P
+// (and P cleared for the iteration after next); one barrier per pass of
+// bins exchanges the per-wave candidate counts and nonzero flags. Other
+// configurations peel straight into the spectra after the transform, with a
+// barrier on each side.
 template <int D, bool kPow2, bool kRecLds, bool kWave>
 __device__ __forceinline__ void solve_cube(const CubeDesc& cd, const float2* __restrict__ x, const OutPtrs out,
                                            const int32_t* __restrict__ sched, const float2* __restrict__ twall,
@@ -240,17 +306,25 @@ __device__ __forceinline__ void solve_cube(const CubeDesc& cd, const float2* __r
   const float gtol = cd.grid_tol;
   const float inv_L = cd.inv_L;
   const int32_t* sch = sched + cd.sched_off;
-  SolveLds s = carve_solve_lds<D>(smem, (int)L, kRecLds ? cd.rec_lds : 0);
+  SolveLds s = carve_solve_lds<D, kWave>(smem, (int)L, kRecLds ? cd.rec_lds : 0);
   for (uint32_t e = tid; e < L; e += B) s.tw[e] = ld_g(twall, cd.tw_off + e);
   const float2* tw = s.tw;
   float2* oamps = (float2*)out.amps;
   const bool use_pf = L <= (uint32_t)(kPfU * B);
   const int wv = tid >> 6;
   const int lane = tid & 63;
+  const int nw = (B + 63) >> 6;
   const int E = (int)(L >> 6);
   // The host sends a cube here only if 64 <= L <= 512 and blockDim has at
   // least D+1 waves.
   constexpr bool wave_path = kWave && kPow2;
+  // Peel concurrently with the transforms when some waves have no line.
+  const bool conc = kRecLds && wave_path && nw > D + 1;
+  // distance between the lines of the spectra
+  const int sstr = wave_path ? wave_scratch_elems((int)L) : (int)L;
+  if (tid == 0) s.cnt[0] = 0;
+  if constexpr (wave_path)
+    for (uint32_t e = tid; e < (D + 1) * L; e += B) s.P[e] = make_float2(0.f, 0.f);
 
   Prefetch<D> pf;
   float2 pfw[kEMax];
@@ -263,11 +337,18 @@ __device__ __forceinline__ void solve_cube(const CubeDesc& cd, const float2* __r
   }
 
   int kc = 0;
+  int xpar = 0;
   int status = kStatusIncomplete;
   int iters = T;
   for (int t = 0; t < T; ++t) {
     const int32_t* at = sch + t * 2 * D;
     const bool precomputed = t < pre_count;
+    uint32_t al[D], ta[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      al[k] = (uint32_t)at[k];
+      ta[k] = (uint32_t)at[D + k];
+    }
     float2* S;
     if constexpr (wave_path) {
       if (wv <= D) {
@@ -282,18 +363,20 @@ __device__ __forceinline__ void solve_cube(const CubeDesc& cd, const float2* __r
           cur[e] = c_scale(pfw[e], sc);
           __asm__ volatile("" : "+v"(cur[e].x), "+v"(cur[e].y));
         }
-        float2* dst = s.bufA + wv * L;
+        // In place: the transform's last reads of its scratch precede its
+        // result stores in this wave's program order, and LDS serves one
+        // wave's accesses in order.
+        float2* dst = s.bufA + wv * wave_scratch_elems((int)L);
         if (precomputed) {
 #pragma unroll
           for (int e = 0; e < kEMax; ++e)
             if (e < E) dst[lane + 64 * e] = cur[e];
         } else {
-          float2* scr = s.bufB + wv * wave_scratch_elems((int)L);
           switch (E) {
-            case 1: wave_fft_to_lds<1>(cur, scr, tw, dst); break;
-            case 2: wave_fft_to_lds<2>(cur, scr, tw, dst); break;
-            case 4: wave_fft_to_lds<4>(cur, scr, tw, dst); break;
-            default: wave_fft_to_lds<8>(cur, scr, tw, dst); break;
+            case 1: wave_fft_to_lds<1>(cur, dst, tw, dst); break;
+            case 2: wave_fft_to_lds<2>(cur, dst, tw, dst); break;
+            case 4: wave_fft_to_lds<4>(cur, dst, tw, dst); break;
+            default: wave_fft_to_lds<8>(cur, dst, tw, dst); break;
           }
         }
         // The next iteration's gathers are issued after the transform: in
@@ -302,74 +385,58 @@ __device__ __forceinline__ void solve_cube(const CubeDesc& cd, const float2* __r
         if (t + 1 < T)
           wave_prefetch<D, kPow2>(pfw, E, g, x, at + 2 * D, pre + (int64_t)(t + 1) * (D + 1) * L, t + 1 < pre_count,
                                   wv);
+      } else if (conc) {
+        const int pt = tid - (D + 1) * 64;
+        peel_records<D, kPow2, kRecLds>(g, al, ta, s, out, tw, pt, B - (D + 1) * 64, kc, s.P, (int)L, 1.0f);
       }
       lds_barrier();
       S = s.bufA;
     } else {
-    if (use_pf) {
-      prefetch_store<D>(pf, L, s.bufA, precomputed ? 1.0f : inv_L);
-    } else if (precomputed) {
-      const float2* src = pre + (int64_t)t * (D + 1) * L;
-      for (uint32_t e = tid; e < (D + 1) * L; e += B) s.bufA[e] = ld_g(src, e);
-    } else {
-      gather_lines<D, kPow2>(s.bufA, x, g, at, 1, inv_L);
-    }
-    lds_barrier();
-    S = precomputed ? s.bufA : block_fft<kPow2>(s.bufA, s.bufB, D + 1, (int)L, cd.nstages, cd.radix, tw);
-    if (use_pf && t + 1 < T)
-      prefetch_issue<D, kPow2>(pf, g, x, at + 2 * D, pre + (int64_t)(t + 1) * (D + 1) * L, t + 1 < pre_count);
-    }
-    uint32_t al[D], ta[D];
-#pragma unroll
-    for (int k = 0; k < D; ++k) {
-      al[k] = (uint32_t)at[k];
-      ta[k] = (uint32_t)at[D + k];
-    }
-
-    // Peel: subtract every earlier record's projection a e^{+j 2 pi p / L}
-    // from bin b of each line, b = [sum_k alpha_k c_k m_k]_L and
-    // p = [sum_k tau_k^{(i)} c_k m_k]_L (Eq. freqSum, Eq. orthogonality).
-    for (int j = tid; j < kc; j += B) {
-      uint32_t gk[D];
-      uint32_t b = 0, p0 = 0;
-#pragma unroll
-      for (int k = 0; k < D; ++k) {
-        const int32_t f = kRecLds ? s.rec_f[j * D + k] : ld_gi(out.freqs, j * D + k);
-        gk[k] = g.c[k] * (uint32_t)f;
-        b = umod<kPow2>(b + al[k] * gk[k], L);
-        p0 = umod<kPow2>(p0 + ta[k] * gk[k], L);
+      if (use_pf) {
+        prefetch_store<D>(pf, L, s.bufA, precomputed ? 1.0f : inv_L);
+      } else if (precomputed) {
+        const float2* src = pre + (int64_t)t * (D + 1) * L;
+        for (uint32_t e = tid; e < (D + 1) * L; e += B) s.bufA[e] = ld_g(src, e);
+      } else {
+        gather_lines<D, kPow2>(s.bufA, x, g, at, 1, inv_L);
       }
-      const float2 a = kRecLds ? s.rec_a[j] : ld_g(oamps, j);
-      float2 c = c_mulc(a, tw[p0]);
-      atomicAdd(&S[b].x, -c.x);
-      atomicAdd(&S[b].y, -c.y);
-#pragma unroll
-      for (int k = 0; k < D; ++k) {
-        uint32_t p = p0 + gk[k];
-        if (p >= L) p -= L;
-        c = c_mulc(a, tw[p]);
-        atomicAdd(&S[(k + 1) * L + b].x, -c.x);
-        atomicAdd(&S[(k + 1) * L + b].y, -c.y);
-      }
+      lds_barrier();
+      S = precomputed ? s.bufA : block_fft<kPow2>(s.bufA, s.bufB, D + 1, (int)L, cd.nstages, cd.radix, tw);
+      if (use_pf && t + 1 < T)
+        prefetch_issue<D, kPow2>(pf, g, x, at + 2 * D, pre + (int64_t)(t + 1) * (D + 1) * L, t + 1 < pre_count);
     }
-    lds_barrier();
+    if (!conc) {
+      peel_records<D, kPow2, kRecLds>(g, al, ta, s, out, tw, tid, B, kc, S, sstr, -1.0f);
+      lds_barrier();
+    }
 
     // Test, decode and append, bins in ascending order.
     bool nonzero = false;
     bool full = false;
+    bool any = false;
     for (uint32_t m0 = 0; m0 < L; m0 += B) {
       const uint32_t m = m0 + tid;
       bool cand = false;
       int f[D];
       float2 amp = make_float2(0.f, 0.f);
       if (m < L) {
-        const float2 r0 = S[m];
+        float2 r[D + 1];
+#pragma unroll
+        for (int i = 0; i <= D; ++i) r[i] = S[i * sstr + m];
+        if (conc) {
+#pragma unroll
+          for (int i = 0; i <= D; ++i) {
+            r[i] = c_sub(r[i], s.P[i * L + m]);
+            s.P[i * L + m] = make_float2(0.f, 0.f);
+          }
+        }
+        const float2 r0 = r[0];
         const float mag0 = sqrtf(r0.x * r0.x + r0.y * r0.y);
         nonzero |= mag0 > th0;
         cand = mag0 > th0;
 #pragma unroll
         for (int k = 0; k < D; ++k) {
-          const float2 ri = S[(k + 1) * L + m];
+          const float2 ri = r[k + 1];
           const float mi = sqrtf(ri.x * ri.x + ri.y * ri.y);
           nonzero |= mi > th0;
           cand = cand && (fabsf(mi - mag0) <= rho * mag0);
@@ -394,17 +461,49 @@ __device__ __forceinline__ void solve_cube(const CubeDesc& cd, const float2* __r
           amp = c_mul(r0, tw[q]);  // r0 exp(-j 2 pi q / L)
         }
       }
-      int tot;
-      const int pos = block_prefix(cand, s.wsum, &tot);
+      int slot = -1;
+      const unsigned long long bal = __ballot(cand ? 1 : 0);
+      const int wcnt = __popcll(bal);
+      const int before = __popcll(bal & ((1ull << lane) - 1ull));
+      if (kRecLds && wcnt > 0) {
+        // Append to the LDS list now (one atomic per wave), so that the next
+        // iteration's peel needs no barrier after the exchange below.
+        const int first = __builtin_ctzll(bal);
+        int base = 0;
+        if (lane == first) base = atomicAdd(s.cnt, wcnt);
+        base = __builtin_amdgcn_readlane(base, first);
+        slot = base + before;
+        if (cand && slot < cd.rec_lds) {
+#pragma unroll
+          for (int k = 0; k < D; ++k) s.rec_f[slot * D + k] = f[k];
+          s.rec_a[slot] = amp;
+          s.rec_t[slot] = t;
+          s.rec_m[slot] = (int32_t)m;
+        }
+      }
+      const bool wnz = __ballot(nonzero ? 1 : 0) != 0ull;
+      if (lane == 0) s.wsum[xpar * 16 + wv] = wcnt | (wnz ? 0x10000 : 0);
+      lds_barrier();
+      // one LDS read per lane, then the words are taken from the lanes
+      const int word = lane < nw ? s.wsum[xpar * 16 + lane] : 0;
+      int pos = before, tot = 0;
+      any = false;
+      for (int w = 0; w < nw; ++w) {
+        const int v = __builtin_amdgcn_readlane(word, w);
+        pos += (w < wv) ? (v & 0xffff) : 0;
+        tot += v & 0xffff;
+        any |= (v >> 16) != 0;
+      }
+      xpar ^= 1;
       if (cand) {
         const int idx = kc + pos;
-        if (idx < max_k) {
+        if (kRecLds && slot < cd.rec_lds) {
+          // written out at the end of the cube (global stores issued now
+          // would queue behind the next iteration's gathers)
+          s.rec_p[slot] = idx;
+        } else if (idx < max_k) {
 #pragma unroll
-          for (int k = 0; k < D; ++k) {
-            if (kRecLds) s.rec_f[idx * D + k] = f[k];
-            st_gi(out.freqs, idx * D + k, f[k]);
-          }
-          if (kRecLds) s.rec_a[idx] = amp;
+          for (int k = 0; k < D; ++k) st_gi(out.freqs, idx * D + k, f[k]);
           st_g(oamps, idx, amp);
           st_gi(out.rec_iter, idx, t);
           st_gi(out.rec_bin, idx, (int32_t)m);
@@ -417,7 +516,6 @@ __device__ __forceinline__ void solve_cube(const CubeDesc& cd, const float2* __r
       }
       kc += tot;
     }
-    const bool nz = block_any(nonzero, s.wsum);
     // Records kept in global memory are read by other threads next
     // iteration: make the stores visible across the work-group.
     if (!kRecLds) __syncthreads();
@@ -426,10 +524,26 @@ __device__ __forceinline__ void solve_cube(const CubeDesc& cd, const float2* __r
       iters = t + 1;
       break;
     }
-    if (!nz) {
+    if (!any) {
       status = kStatusOk;
       iters = t + 1;
       break;
+    }
+  }
+  if constexpr (kRecLds) {
+    // The LDS record list, in the order the waves appended it, goes to its
+    // canonical positions (entries past the capacity are dropped).
+    lds_barrier();
+    const int n = min(s.cnt[0], cd.rec_lds);
+    for (int j = tid; j < n; j += B) {
+      const int idx = s.rec_p[j];
+      if (idx < max_k) {
+#pragma unroll
+        for (int k = 0; k < D; ++k) st_gi(out.freqs, idx * D + k, s.rec_f[j * D + k]);
+        st_g(oamps, idx, s.rec_a[j]);
+        st_gi(out.rec_iter, idx, s.rec_t[j]);
+        st_gi(out.rec_bin, idx, s.rec_m[j]);
+      }
     }
   }
   if (tid == 0) {

@@ -207,7 +207,7 @@ fpssft_status hip_status(hipError_t e) {
 }  // namespace
 
 // Cubes served by one kernel instantiation: a contiguous slice of the
-// order array (longest lines first) and of the line-FFT item list.
+// order array (shortest lines first) and of the line-FFT item list.
 struct Group {
   fpssft::KernelKey key;
   int first = 0;        // into order[]
@@ -260,11 +260,17 @@ struct fpssft_plan_st {
 
 namespace {
 
+// Cubes the one-wave-per-line path can take (power-of-two 64 <= L <= 512).
+bool wave_eligible(const CubeDesc& c) { return c.Lmask >= 0 && c.L >= 64 && c.L <= 512; }
+
 size_t solve_lds_bytes(const CubeDesc& c, int rec_lds) {
-  // line buffer, second buffer / wave-FFT scratch (9/8 of the lines), twiddles
+  // Lines, second buffer or padded rows plus peel accumulator (both layouts
+  // take 2 (D+1) L + (D+1) L / 8 values), twiddles; per record the
+  // amplitude, D frequency indices, output position, iteration and bin;
+  // the exchange words.
   const size_t lines = (size_t)(c.D + 1) * c.L;
   size_t b = (2 * lines + lines / 8 + c.L) * sizeof(float2);
-  b += (size_t)rec_lds * sizeof(float2) + (size_t)rec_lds * c.D * sizeof(int32_t);
+  b += (size_t)rec_lds * (sizeof(float2) + (c.D + 3) * sizeof(int32_t));
   b += 64 * sizeof(int);
   return b;
 }
@@ -281,7 +287,7 @@ size_t lines_single_lds_bytes(const CubeDesc& c) { return lines_lds_bytes(c.D, c
 fpssft::KernelKey key_of(const fpssft_plan_t p, int c) {
   const CubeDesc& cd = p->descs[c];
   const bool pow2 = cd.Lmask >= 0;
-  const bool wave = pow2 && cd.L >= 64 && cd.L <= 512 && p->tune.block_threads / 64 >= cd.D + 1;
+  const bool wave = wave_eligible(cd) && p->tune.block_threads / 64 >= cd.D + 1;
   return fpssft::KernelKey{cd.D, pow2, p->rec_lds, wave};
 }
 
@@ -395,8 +401,9 @@ fpssft_status build_plan(const fpssft_desc* descs, int32_t batch, const fpssft_t
   }
   for (auto& cd : p->descs) cd.rec_lds = p->rec_lds ? cd.max_k : 0;
 
-  // Group cubes by kernel instantiation; within a group, longest lines first
-  // (the per-iteration cost grows with (D+1) L), ties by index.
+  // Group cubes by kernel instantiation; within a group, shortest lines
+  // first, ties by index: short lines hold more sinusoids per bin, and their
+  // long runs of cheap iterations set the makespan when started late.
   p->group_of.assign(batch, -1);
   for (int32_t c = 0; c < batch; ++c) {
     const fpssft::KernelKey k = key_of(p, c);
@@ -417,7 +424,7 @@ fpssft_status build_plan(const fpssft_desc* descs, int32_t batch, const fpssft_t
     if (p->group_of[a] != p->group_of[b]) return p->group_of[a] < p->group_of[b];
     const int64_t ca = (int64_t)(p->descs[a].D + 1) * p->descs[a].L;
     const int64_t cb = (int64_t)(p->descs[b].D + 1) * p->descs[b].L;
-    return ca > cb;
+    return ca < cb;
   });
   const int threads = tn.block_threads;
   for (size_t gi = 0; gi < p->groups.size(); ++gi) {

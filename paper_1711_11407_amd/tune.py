@@ -27,7 +27,7 @@ import time
 
 DEFAULT_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning.json")
 
-SOLVE_GRID = dict(block_threads=(64, 128, 256, 512), max_radix=(4, 8))
+SOLVE_GRID = dict(block_threads=(64, 128, 192, 256, 320, 384, 448, 512), max_radix=(4, 8))
 LINES_GRID = dict(lines_wg=(1, 2, 4, 8), lines_threads=(64, 128, 256, 512))
 PLAIN_GRID = dict(chunk_iters=(0, 2, 4, 8, 16))
 
