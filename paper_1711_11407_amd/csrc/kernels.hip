@@ -568,8 +568,11 @@ __global__ FPS_SOLVE_ATTRS void k_solve_plain(const CubeDesc* __restrict__ descs
 }
 
 // Persistent: every work-group loops taking the next cube of `order` from
-// the queue counter; it leaves when the counter passes the cube count, so
-// every wave reaches the exit.
+// the queue counter queue[0]; it leaves when the counter passes the cube
+// count, so every wave reaches the exit. Leaving, it counts itself in
+// queue[1]; the last work-group out (every other one has made its final
+// take) sets both counters back to zero for the next launch, so no reset
+// kernel precedes the launch.
 template <int D, bool kPow2, bool kRecLds, bool kWave>
 __global__ FPS_SOLVE_ATTRS void k_solve_batched(const CubeDesc* __restrict__ descs, const float2* const* __restrict__ xs,
                                 const OutPtrs* __restrict__ outs, const int32_t* __restrict__ sched,
@@ -583,7 +586,13 @@ __global__ FPS_SOLVE_ATTRS void k_solve_batched(const CubeDesc* __restrict__ des
     // uniform across the work-group: keep it in a scalar register
     const int idx = __builtin_amdgcn_readfirstlane(s_idx);
     __syncthreads();
-    if (idx >= ncubes) break;
+    if (idx >= ncubes) {
+      if (threadIdx.x == 0 && atomicAdd(queue + 1, 1) == (int)gridDim.x - 1) {
+        atomicExch(queue, 0);
+        atomicExch(queue + 1, 0);
+      }
+      break;
+    }
     const int c = __builtin_amdgcn_readfirstlane(order[idx]);
     solve_cube<D, kPow2, kRecLds, kWave>(descs[c], xs[c], outs[c], sched, tw, nullptr, 0, lds_solve);
   }

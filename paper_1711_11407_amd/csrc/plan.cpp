@@ -511,8 +511,10 @@ fpssft_status build_plan(const fpssft_desc* descs, int32_t batch, const fpssft_t
   if (max_pre > 0) HIP_TRY(hipMalloc(&p->d_pre, sizeof(float2) * max_pre));
   HIP_TRY(hipMalloc(&p->d_order, sizeof(int32_t) * batch));
   HIP_TRY(hipMemcpy(p->d_order, order.data(), sizeof(int32_t) * batch, hipMemcpyHostToDevice));
-  HIP_TRY(hipMalloc(&p->d_queue, sizeof(int) * std::max<size_t>(p->groups.size(), 1)));
-  HIP_TRY(hipMemset(p->d_queue, 0, sizeof(int) * std::max<size_t>(p->groups.size(), 1)));
+  // per group: the persistent solve's queue counter and exit counter (the
+  // kernel leaves both at zero)
+  HIP_TRY(hipMalloc(&p->d_queue, 2 * sizeof(int) * std::max<size_t>(p->groups.size(), 1)));
+  HIP_TRY(hipMemset(p->d_queue, 0, 2 * sizeof(int) * std::max<size_t>(p->groups.size(), 1)));
   HIP_TRY(hipMalloc(&p->d_items, sizeof(LineItem) * std::max<size_t>(p->items.size(), 1)));
   HIP_TRY(hipMemcpy(p->d_items, p->items.data(), sizeof(LineItem) * p->items.size(), hipMemcpyHostToDevice));
   HIP_TRY(hipMalloc(&p->d_ranges, sizeof(int32_t) * p->ranges.size()));
@@ -656,15 +658,16 @@ fpssft_status fpssft_execute_batched(fpssft_plan_t p, const void* const* xs, con
   HIP_TRY(p->xs_tab.update(xs, st));
   HIP_TRY(p->outs_tab.update(op.data(), st));
   if (!p->gexec) {
-    // One graph: reset every group's queue counter, then one persistent
-    // launch per group.
+    // One graph: one persistent launch per group (each launch finds its
+    // queue counters at zero and leaves them so).
     HIP_TRY(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
-    hipError_t e = fpssft::launch_reset(p->d_queue, (int)p->groups.size(), p->cap_stream);
+    hipError_t e = hipSuccess;
     for (size_t gi = 0; e == hipSuccess && gi < p->groups.size(); ++gi) {
       const Group& g = p->groups[gi];
       e = fpssft::launch_solve_batched(p->ctx, g.key, (const float2* const*)p->xs_tab.dev,
                                        (const OutPtrs*)p->outs_tab.dev, p->d_order + g.first, g.count,
-                                       p->d_queue + gi, g.grid, g.lds_solve, p->tune.block_threads, p->cap_stream);
+                                       p->d_queue + 2 * gi, g.grid, g.lds_solve, p->tune.block_threads,
+                                       p->cap_stream);
     }
     hipGraph_t graph = nullptr;
     hipError_t e2 = hipStreamEndCapture(p->cap_stream, &graph);
