@@ -280,6 +280,48 @@ __device__ __forceinline__ void peel_records(const Geo<D>& g, const uint32_t (&a
   }
 }
 
+// Bin m of one iteration (r: its value on lines 0..D after the peel): the
+// nonzero and magnitude-equality tests (Sec. 2.1), the phase decode of the
+// frequency (Eq. decoding) with the on-grid check, the projection-consistency
+// check, and the amplitude r_0 exp(-j 2 pi q / L). All decisions in float32.
+template <int D, bool kPow2>
+__device__ __forceinline__ bool decode_bin(const Geo<D>& g, const uint32_t (&al)[D], const uint32_t (&ta)[D],
+                                           const float2 (&r)[D + 1], uint32_t m, float th0, float rho, float gtol,
+                                           const float2* tw, bool& nonzero, int (&f)[D], float2& amp) {
+  const uint32_t L = g.L;
+  const float2 r0 = r[0];
+  const float mag0 = sqrtf(r0.x * r0.x + r0.y * r0.y);
+  nonzero |= mag0 > th0;
+  bool cand = mag0 > th0;
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    const float2 ri = r[k + 1];
+    const float mi = sqrtf(ri.x * ri.x + ri.y * ri.y);
+    nonzero |= mi > th0;
+    cand = cand && (fabsf(mi - mag0) <= rho * mag0);
+    const float2 z = c_mulc(ri, r0);
+    const float phi = atan2f(z.y, z.x);
+    const float u = ((float)g.dims[k] * phi) * kInv2Pi;
+    const float v = rintf(u);
+    if (gtol >= 0.f) cand = cand && (fabsf(u - v) <= gtol);
+    int fi = (int)v % (int)g.dims[k];
+    if (fi < 0) fi += (int)g.dims[k];
+    f[k] = fi;
+  }
+  if (cand) {
+    uint32_t b = 0, q = 0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      const uint32_t gk = g.c[k] * (uint32_t)f[k];
+      b = umod<kPow2>(b + al[k] * gk, L);
+      q = umod<kPow2>(q + ta[k] * gk, L);
+    }
+    cand = (b == m);
+    amp = c_mul(r0, tw[q]);  // r0 exp(-j 2 pi q / L)
+  }
+  return cand;
+}
+
 // kRecLds: the record list lives in LDS (in the order the work-group's waves
 // appended it, which the peel does not depend on) and is written to the
 // outputs in canonical order; otherwise the peel reads the outputs.
@@ -430,36 +472,7 @@ __device__ __forceinline__ void solve_cube(const CubeDesc& cd, const float2* __r
             s.P[i * L + m] = make_float2(0.f, 0.f);
           }
         }
-        const float2 r0 = r[0];
-        const float mag0 = sqrtf(r0.x * r0.x + r0.y * r0.y);
-        nonzero |= mag0 > th0;
-        cand = mag0 > th0;
-#pragma unroll
-        for (int k = 0; k < D; ++k) {
-          const float2 ri = r[k + 1];
-          const float mi = sqrtf(ri.x * ri.x + ri.y * ri.y);
-          nonzero |= mi > th0;
-          cand = cand && (fabsf(mi - mag0) <= rho * mag0);
-          const float2 z = c_mulc(ri, r0);
-          const float phi = atan2f(z.y, z.x);
-          const float u = ((float)g.dims[k] * phi) * kInv2Pi;
-          const float v = rintf(u);
-          if (gtol >= 0.f) cand = cand && (fabsf(u - v) <= gtol);
-          int fi = (int)v % (int)g.dims[k];
-          if (fi < 0) fi += (int)g.dims[k];
-          f[k] = fi;
-        }
-        if (cand) {
-          uint32_t b = 0, q = 0;
-#pragma unroll
-          for (int k = 0; k < D; ++k) {
-            const uint32_t gk = g.c[k] * (uint32_t)f[k];
-            b = umod<kPow2>(b + al[k] * gk, L);
-            q = umod<kPow2>(q + ta[k] * gk, L);
-          }
-          cand = (b == m);
-          amp = c_mul(r0, tw[q]);  // r0 exp(-j 2 pi q / L)
-        }
+        cand = decode_bin<D, kPow2>(g, al, ta, r, m, th0, rho, gtol, tw, nonzero, f, amp);
       }
       int slot = -1;
       const unsigned long long bal = __ballot(cand ? 1 : 0);
