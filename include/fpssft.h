@@ -148,7 +148,12 @@ fpssft_status fpssft_schedule_generate(const fpssft_desc* desc, int32_t T,
 /* Build a plan for `batch` cubes on the current HIP device: validates every
  * description, draws or copies the schedules, builds twiddle tables
  * W_L^k = exp(-j 2 pi k / L) (fp64 on the host, rounded to fp32) and FFT
- * factorisations, and uploads them. `tuning` may be NULL. */
+ * factorisations, and uploads them. `tuning` may be NULL.
+ * Lines whose D+1 spectra, a second buffer and the twiddles do not fit in
+ * LDS (160 KB) are transformed one line at a time, with the twiddles read
+ * from device memory; UNSUPPORTED when even the D+1 spectra plus one line of
+ * scratch do not fit ((D+2) L * 8 bytes > 160 KB less the record list,
+ * e.g. L > 5000 for D = 2). */
 fpssft_status fpssft_plan_create(const fpssft_desc* descs, int32_t batch,
                                  const fpssft_tuning* tuning, fpssft_plan_t* plan);
 
@@ -180,7 +185,7 @@ fpssft_status fpssft_execute(fpssft_plan_t plan, int32_t cube, const void* x,
                              const fpssft_out* out, void* stream);
 
 /* All cubes of the plan in one persistent launch (work-groups take cubes
- * from a device queue, longest first), replayed from a HIP graph. xs: host
+ * from a device queue, shortest lines first), replayed from a HIP graph. xs: host
  * array of `batch` device cube pointers; outs: host array of `batch` output
  * structs. Results equal fpssft_execute's cube by cube. */
 fpssft_status fpssft_execute_batched(fpssft_plan_t plan, const void* const* xs,

@@ -443,6 +443,25 @@ __device__ __forceinline__ void load_line_samples(const float2* __restrict__ x, 
 }
 
 // ---------------------------------------------------------------------------
+// Line i (0..D) of one iteration alone: dst[l] = scale * sample l (Eq.
+// sample_slice), row: the iteration's slope and offsets [2][D]. Whole
+// work-group.
+// ---------------------------------------------------------------------------
+template <int D, bool kPow2>
+__device__ __forceinline__ void gather_one_line(float2* __restrict__ dst, const float2* __restrict__ x,
+                                                const Geo<D>& g, const int32_t* __restrict__ row, int i,
+                                                float scale) {
+  for (uint32_t l = threadIdx.x; l < g.L; l += blockDim.x) {
+    int64_t step[D];
+    int64_t flat = line_sample<D, kPow2>(g, row, l, step);
+#pragma unroll
+    for (int k = 0; k < D; ++k)
+      if (i == k + 1) flat += step[k];
+    dst[l] = c_scale(ld_g(x, flat), scale);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Line gather: the D+1 lines of `nt` consecutive iterations, sample l of
 // line i of iteration tt written (times `scale`) to dst[(tt (D+1) + i) L + l].
 // at: the schedule rows [nt][2][D]. Each thread issues the loads of kU

@@ -88,6 +88,27 @@ __device__ __forceinline__ void lines_item(const CubeDesc& cd, const float2* __r
   const Geo<D> g = load_geo<D>(cd);
   const uint32_t L = g.L;
   const int B = blockDim.x;
+  if (cd.serial) {
+    // Long lines: one line at a time through two line buffers at the start
+    // of LDS (which may cover the cached twiddles: the cache is dropped),
+    // twiddles from global memory.
+    float2* X = bufA;
+    float2* Y = X + L;
+    const float2* twg = twall + cd.tw_off;
+    const int32_t* sch = sched + cd.sched_off + tb * 2 * D;
+    for (int i = 0; i < tc; ++i) {
+      for (int line = 0; line <= D; ++line) {
+        gather_one_line<D, kPow2>(X, x, g, sch + i * 2 * D, line, cd.inv_L);
+        lds_barrier();
+        const float2* S = block_fft<kPow2>(X, Y, 1, (int)L, cd.nstages, cd.radix, twg);
+        float2* o = out + ((int64_t)i * (D + 1) + line) * L;
+        for (uint32_t e = threadIdx.x; e < L; e += B) st_g(o, e, S[e]);
+        lds_barrier();
+      }
+    }
+    *tw_cached = -1;
+    return;
+  }
   if (*tw_cached != cd.tw_off) {  // uniform
     lds_barrier();
     for (uint32_t e = threadIdx.x; e < L; e += B) tw[e] = ld_g(twall, cd.tw_off + e);
@@ -173,10 +194,15 @@ struct SolveLds {
 // runs in place there) followed by the peel accumulator, the block path two
 // line buffers.
 template <int D, bool kWave>
-__device__ __forceinline__ SolveLds carve_solve_lds(char* smem, int L, int rec_lds) {
+__device__ __forceinline__ SolveLds carve_solve_lds(char* smem, int L, int rec_lds, bool serial) {
   SolveLds s;
   s.bufA = (float2*)smem;
-  if constexpr (kWave) {
+  if (!kWave && serial) {
+    // long lines: the spectra, one line of scratch, no twiddles (global)
+    s.bufB = s.bufA + (D + 1) * L;
+    s.P = nullptr;
+    s.tw = s.bufB + L;
+  } else if constexpr (kWave) {
     s.bufB = nullptr;
     s.P = s.bufA + (D + 1) * wave_scratch_elems(L);
     s.tw = s.P + (D + 1) * L;
@@ -185,7 +211,7 @@ __device__ __forceinline__ SolveLds carve_solve_lds(char* smem, int L, int rec_l
     s.P = nullptr;
     s.tw = s.bufB + wave_scratch_elems((D + 1) * L);
   }
-  s.rec_a = s.tw + L;
+  s.rec_a = s.tw + (!kWave && serial ? 0 : L);
   s.rec_f = (int32_t*)(s.rec_a + rec_lds);
   s.rec_p = s.rec_f + rec_lds * D;
   s.rec_t = s.rec_p + rec_lds;
@@ -348,11 +374,15 @@ __device__ __forceinline__ void solve_cube(const CubeDesc& cd, const float2* __r
   const float gtol = cd.grid_tol;
   const float inv_L = cd.inv_L;
   const int32_t* sch = sched + cd.sched_off;
-  SolveLds s = carve_solve_lds<D, kWave>(smem, (int)L, kRecLds ? cd.rec_lds : 0);
-  for (uint32_t e = tid; e < L; e += B) s.tw[e] = ld_g(twall, cd.tw_off + e);
-  const float2* tw = s.tw;
+  // Long lines (block path only): lines transformed one at a time, twiddles
+  // read from global memory (the host sends no precomputed spectra).
+  const bool serial = !(kWave && kPow2) && cd.serial != 0;
+  SolveLds s = carve_solve_lds<D, kWave>(smem, (int)L, kRecLds ? cd.rec_lds : 0, serial);
+  if (!serial)
+    for (uint32_t e = tid; e < L; e += B) s.tw[e] = ld_g(twall, cd.tw_off + e);
+  const float2* tw = serial ? twall + cd.tw_off : s.tw;
   float2* oamps = (float2*)out.amps;
-  const bool use_pf = L <= (uint32_t)(kPfU * B);
+  const bool use_pf = !serial && L <= (uint32_t)(kPfU * B);
   const int wv = tid >> 6;
   const int lane = tid & 63;
   const int nw = (B + 63) >> 6;
@@ -432,6 +462,18 @@ __device__ __forceinline__ void solve_cube(const CubeDesc& cd, const float2* __r
         peel_records<D, kPow2, kRecLds>(g, al, ta, s, out, tw, pt, B - (D + 1) * 64, kc, s.P, (int)L, 1.0f);
       }
       lds_barrier();
+      S = s.bufA;
+    } else if (serial) {
+      for (int line = 0; line <= D; ++line) {
+        gather_one_line<D, kPow2>(s.bufB, x, g, at, line, inv_L);
+        lds_barrier();
+        float2* dst = s.bufA + line * L;
+        const float2* R = block_fft<kPow2>(s.bufB, dst, 1, (int)L, cd.nstages, cd.radix, tw);
+        if (R != dst) {
+          for (uint32_t e = tid; e < L; e += B) dst[e] = R[e];
+          lds_barrier();
+        }
+      }
       S = s.bufA;
     } else {
       if (use_pf) {

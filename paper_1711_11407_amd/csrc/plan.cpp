@@ -219,7 +219,8 @@ struct Group {
   size_t lds_bwd = 0;
   size_t lds_lines = 0;
   int lines_grid = 0;   // persistent line-FFT grid (multiple of 8)
-  int32_t maxL = 1;
+  int32_t maxL = 1;         // longest line of the group's regular cubes
+  int32_t maxL_serial = 0;  // longest line of its long-line cubes
   int64_t max_N = 0;
 };
 
@@ -264,6 +265,12 @@ namespace {
 bool wave_eligible(const CubeDesc& c) { return c.Lmask >= 0 && c.L >= 64 && c.L <= 512; }
 
 size_t solve_lds_bytes(const CubeDesc& c, int rec_lds) {
+  if (c.serial) {
+    // long lines: the D+1 spectra and one line of scratch
+    size_t b = (size_t)(c.D + 2) * c.L * sizeof(float2);
+    b += (size_t)rec_lds * (sizeof(float2) + (c.D + 3) * sizeof(int32_t));
+    return b + 64 * sizeof(int);
+  }
   // Lines, second buffer or padded rows plus peel accumulator (both layouts
   // take 2 (D+1) L + (D+1) L / 8 values), twiddles; per record the
   // amplitude, D frequency indices, output position, iteration and bin;
@@ -282,7 +289,9 @@ size_t bwd_lds_bytes(const CubeDesc& c) {
 // Line-FFT work-group LDS: two line buffers and the twiddle table.
 size_t lines_lds_bytes(int D, int L) { return (2 * (size_t)(D + 1) + 1) * L * sizeof(float2); }
 
-size_t lines_single_lds_bytes(const CubeDesc& c) { return lines_lds_bytes(c.D, c.L); }
+size_t lines_single_lds_bytes(const CubeDesc& c) {
+  return c.serial ? 2 * (size_t)c.L * sizeof(float2) : lines_lds_bytes(c.D, c.L);
+}
 
 fpssft::KernelKey key_of(const fpssft_plan_t p, int c) {
   const CubeDesc& cd = p->descs[c];
@@ -390,7 +399,11 @@ fpssft_status build_plan(const fpssft_desc* descs, int32_t batch, const fpssft_t
     cd.tw_off = it->second;
     cd.spec_off = p->spec_elems;
     p->spec_elems += (int64_t)T * (d.ndim + 1) * L;
-    const int32_t pre_T = std::min(T, tn.chunk_iters);
+    // Lines too long for the D+1 spectra plus a second buffer and the
+    // twiddles in LDS are transformed one at a time (no precomputed chunk).
+    cd.serial = 0;
+    if (!wave_eligible(cd) && solve_lds_bytes(cd, 0) > p->lds_max) cd.serial = 1;
+    const int32_t pre_T = cd.serial ? 0 : std::min(T, tn.chunk_iters);
     max_pre = std::max<int64_t>(max_pre, (int64_t)pre_T * (d.ndim + 1) * L);
     p->max_N = std::max(p->max_N, cd.N);
     if (solve_lds_bytes(cd, 0) > p->lds_max || lines_single_lds_bytes(cd) > p->lds_max)
@@ -445,7 +458,10 @@ fpssft_status build_plan(const fpssft_desc* descs, int32_t batch, const fpssft_t
     for (int i = g.first; i < g.first + g.count; ++i) {
       const int32_t c = order[i];
       const CubeDesc& cd = p->descs[c];
-      g.maxL = std::max(g.maxL, cd.L);
+      if (cd.serial)
+        g.maxL_serial = std::max(g.maxL_serial, cd.L);
+      else
+        g.maxL = std::max(g.maxL, cd.L);
       for (int32_t t = 0; t < cd.T; t += tn.lines_wg) {
         LineItem li{};
         li.cube = c;
@@ -456,7 +472,7 @@ fpssft_status build_plan(const fpssft_desc* descs, int32_t batch, const fpssft_t
       }
     }
     g.item_count = (int)p->items.size() - g.item_first;
-    g.lds_lines = lines_lds_bytes(g.key.D, g.maxL);
+    g.lds_lines = std::max(lines_lds_bytes(g.key.D, g.maxL), 2 * (size_t)g.maxL_serial * sizeof(float2));
     if (g.lds_lines > p->lds_max) return FPSSFT_ERR_UNSUPPORTED;
     // Eight contiguous item ranges of about equal work ((D+1) L per iteration).
     {
@@ -636,7 +652,7 @@ fpssft_status fpssft_execute(fpssft_plan_t p, int32_t cube, const void* x, const
   const CubeDesc& cd = p->descs[cube];
   const fpssft::KernelKey key = key_of(p, cube);
   const Group& g = p->groups[p->group_of[cube]];
-  const int pre = std::min(cd.T, p->tune.chunk_iters);
+  const int pre = cd.serial ? 0 : std::min(cd.T, p->tune.chunk_iters);
   if (pre > 0) {
     HIP_TRY(fpssft::launch_lines_single(p->ctx, key, cube, (const float2*)x, 0, pre, p->d_pre, cd.L,
                                         lines_single_lds_bytes(cd), p->tune.lines_threads, st));

@@ -26,7 +26,8 @@ struct CubeDesc {
   int32_t sched_off;         // int32 offset of [T][2][D] in the schedule table
   int32_t tw_off;            // float2 offset of W_L in the twiddle table
   int32_t rec_lds;           // records kept in LDS (capacity), 0: global
-  int32_t pad0;
+  int32_t serial;            // long lines: transformed one at a time through a
+                             // one-line scratch, twiddles read from global memory
   int64_t spec_off;          // element offset in the packed spectra buffer
 };
 

@@ -209,3 +209,64 @@ def test_lines_fft_all_mixed_lengths_matches_single(F):
                 want = O.line_dft(O.gather_line(x64, sched[t, 0], offs, L))
                 err = np.abs(blk[t, i] - want).max() / max(np.linalg.norm(want), 1e-30)
                 assert err < 1e-5, (d, t, i, err)
+
+
+# Long lines (L = LCM too long for the D+1 spectra, a second buffer and the
+# twiddles in LDS): transformed one line at a time. 512 x 576 is the shape of
+# the paper's image experiment (Sec. 3), L = 4608 = 2^9 3^2; 2048 x 4096 is a
+# power-of-two line length past the in-LDS limit.
+LONG = [((512, 576), 300, 0), ((6000,), 40, 3), ((2048, 4096), 200, 0)]
+
+
+@pytest.mark.parametrize("dims,K,T", LONG)
+def test_long_lines_plain_and_batched(F, dims, K, T):
+    torch, dev = torch_dev()
+    cube = W.plant(dims, K, seed=400 + K, mag=(0.5, 1.5))
+    short = W.plant((64, 128), 30, seed=401)
+    specs = [spec_for(F, dims, 402, max_iters=T, max_k=512), spec_for(F, short.dims, 403, max_k=64)]
+    log(f"long lines dims={dims} K={K} L={O.line_length(dims)}")
+    plan = F.Plan(specs)
+    xs = [torch.from_numpy(cube.x).to(dev), torch.from_numpy(short.x).to(dev)]
+    plain = [plan.execute(c, xs[c]).host() for c in range(2)]
+    batched = [o.host() for o in plan.execute_batched(xs)]
+    for c, x in enumerate((cube.x, short.x)):
+        ref, _, _ = oracle_for(plan, c, x, specs[c])
+        compare(plain[c], ref, f"plain {c}")
+        compare(batched[c], ref, f"batched {c}")
+    assert plain[0]["status"] == O.STATUS_OK
+    assert {tuple(f) for f in plain[0]["freqs"].tolist()} == {tuple(f) for f in cube.freqs.tolist()}
+
+
+def test_long_lines_fft_matches_oracle_line_dft(F):
+    torch, dev = torch_dev()
+    dims = (512, 576)
+    x = W.random_dense(dims, 17).astype(np.complex64)
+    spec = spec_for(F, dims, 9, max_iters=4)
+    plan = F.Plan([spec, spec_for(F, (64, 64), 10, max_iters=3)])
+    xt = torch.from_numpy(x).to(dev)
+    one = plan.lines_fft(0, xt, 0, 4).cpu().numpy()
+    allsp = plan.lines_fft_all([xt, torch.from_numpy(W.random_dense((64, 64), 3).astype(np.complex64)).to(dev)])
+    L, T, off = plan.info[0]
+    blk = allsp.cpu().numpy()[off:off + T * 3 * L].reshape(T, 3, L)
+    sched = plan.schedule(0)
+    for t in range(4):
+        for i, offs in enumerate(O.line_offsets(dims, sched[t, 1])):
+            want = O.line_dft(O.gather_line(x.astype(np.complex128), sched[t, 0], offs, L))
+            for got in (one[t, i], blk[t, i]):
+                err = np.abs(got - want).max() / max(np.linalg.norm(want), 1e-30)
+                assert err < 1e-5, (t, i, err)
+
+
+def test_image_scale_sparsity(F):
+    """K = 8411 on 512 x 576 (the sparsity of the paper's first image, 2.85%
+    nonzero): same records as the oracle; the paper needs 14.0% of the
+    samples (3 iterations) for its image, the iteration count here is logged."""
+    torch, dev = torch_dev()
+    cube = W.plant((512, 576), 8411, seed=8411)
+    spec = spec_for(F, cube.dims, 8412, max_k=16384)
+    plan, got = run_plain(F, cube.x, spec)
+    ref, _, _ = oracle_for(plan, 0, cube.x, spec)
+    compare(got, ref, "image scale")
+    log(f"K=8411 on 512x576: status {got['status']} after {got['iters']} iterations "
+        f"({100.0 * got['iters'] * 3 * 4608 / (512 * 576):.1f}% of the samples)")
+    assert got["status"] == O.STATUS_OK
