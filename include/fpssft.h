@@ -36,7 +36,7 @@ extern "C" {
 #endif
 
 #define FPSSFT_MAX_D 4
-#define FPSSFT_ABI_VERSION 1
+#define FPSSFT_ABI_VERSION 2
 
 /* Return codes (negative) and device-side outcomes (non-negative). */
 typedef enum {
@@ -63,6 +63,8 @@ typedef enum {
  *               for every shifted line i (the magnitude test of Sec. 2.1).
  *  grid_tol     gamma: the decoded u_k = N_k phi / (2 pi) must be within
  *               gamma of an integer; gamma < 0 disables the check.
+ *  flags        FPSSFT_FLAG_* below, OR-ed; 0 is the paper's method with
+ *               the frequency-domain peel.
  *  schedule     optional host array int32 [max_iters][2][ndim]: per
  *               iteration the slope alpha then the offset tau, entries in
  *               [0, N_k). NULL: drawn from `seed` (fpssft_schedule_generate).
@@ -77,8 +79,32 @@ typedef struct {
   float zero_thresh;
   float mag_rel_tol;
   float grid_tol;
+  uint32_t flags;
   const int32_t* schedule;
 } fpssft_desc;
+
+/* Variants of the method (fpssft_desc.flags).
+ *  AXIS_SCHEDULE  generated schedule with axis-aligned slopes: iteration t
+ *                 uses alpha = e_{t mod D} (the row/column lines of the
+ *                 earlier 2-D sparse FFT that Sec. 2.1 reviews, and whose
+ *                 deadlock on grid-shaped supports Sec. 2.2 describes); the
+ *                 offsets are drawn as in the default schedule, D draws per
+ *                 iteration from the same SplitMix64 stream, and no slope is
+ *                 drawn. Ignored when `schedule` is given.
+ *  AMP_AVERAGE    amplitude of a decoded bin averaged over the D+1 lines,
+ *                 a = (1/(D+1)) sum_i r_i(m) W_L^{q_i}, q_i = [sum_k c_k m_k
+ *                 tau_k^{(i)}]_L, instead of line 0 alone (Eq. decoding uses
+ *                 line 0; for noisy data the average has 1/(D+1) of the
+ *                 variance). fpssft_amp_backward returns UNSUPPORTED.
+ *  LITERAL_PEEL   construction-subtraction as the paper states it (Sec. 2.2):
+ *                 the recovered records' line spectra are inverse transformed
+ *                 and subtracted from the gathered samples before the line
+ *                 DFT, instead of being subtracted from the line spectra.
+ *                 Equal up to rounding; slower (two more transforms per
+ *                 line). UNSUPPORTED together with lines too long for LDS. */
+#define FPSSFT_FLAG_AXIS_SCHEDULE 0x1u
+#define FPSSFT_FLAG_AMP_AVERAGE 0x2u
+#define FPSSFT_FLAG_LITERAL_PEEL 0x4u
 
 /* Per-cube outputs: all DEVICE pointers, caller-owned.
  *  freqs     int32 [max_k][ndim]  recovered frequency indices m_k in [0, N_k)
@@ -135,7 +161,8 @@ fpssft_status fpssft_validate(const fpssft_desc* desc, int32_t* line_length,
 
 /* The line schedule that `desc` (with schedule == NULL) produces: host
  * array int32 [T][2][ndim], iterations 0..T-1 (Sec. 2.2: a random slope in
- * Lemma 2's set and a random offset each iteration). One SplitMix64 stream
+ * Lemma 2's set and a random offset each iteration; with
+ * FPSSFT_FLAG_AXIS_SCHEDULE, axis slopes and random offsets). One SplitMix64 stream
  * (Steele, Lea, Flood 2014) per cube, output i = mix(seed + (i+1) * 0x9E37...).
  * A draw on [0, n) is floor(z * n / 2^64). Per iteration: draw alpha_0..
  * alpha_{D-1}, redraw all D until gcd(c_0 alpha_0, ..., c_{D-1} alpha_{D-1})

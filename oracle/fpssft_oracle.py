@@ -114,13 +114,17 @@ def _below(z: int, n: int) -> int:
     return (z * int(n)) >> 64
 
 
-def schedule(dims: Sequence[int], T: int, seed: int):
+def schedule(dims: Sequence[int], T: int, seed: int, axis: bool = False):
     """Per-iteration slope and offset (Sec. 2.2: a random slope from Lemma 2's
     set and a random offset each iteration; D-D: both from X_D).
 
     Draw order, one counter stream per cube: for each iteration, draw the D
     slope components (uniform on [N_k]) and redraw all D until the slope is
     in A; then draw the D offset components (uniform on [N_k]).
+
+    axis=True: the slopes of the row/column method reviewed in Sec. 2.1 and
+    shown to deadlock in Sec. 2.2, alpha = e_{t mod D} (the unit vector,
+    reduced mod N_k), with no slope drawn; offsets as above.
     Returns int64 arrays alpha [T, D] and tau [T, D].
     """
     dims = [int(d) for d in dims]
@@ -129,13 +133,15 @@ def schedule(dims: Sequence[int], T: int, seed: int):
     tau = np.zeros((T, D), dtype=np.int64)
     ctr = 0
     for t in range(T):
-        while True:
+        while not axis:
             a = []
             for k in range(D):
                 a.append(_below(splitmix64(seed, ctr), dims[k]))
                 ctr += 1
             if in_slope_set(a, dims):
                 break
+        if axis:
+            a = [(1 if k == t % D else 0) % dims[k] for k in range(D)]
         alpha[t] = a
         for k in range(D):
             tau[t, k] = _below(splitmix64(seed, ctr), dims[k])
@@ -225,6 +231,9 @@ class Params:
     grid_tol: float = 1e-2      # gamma: |u - rint(u)| <= gamma (< 0: off)
     max_iters: int = 0          # 0: floor(N / ((D+1) L))
     max_k: int = 4096           # capacity of the record list
+    amp_average: bool = False   # amplitude: mean over the D+1 lines of
+                                # r_i(m) exp(-j 2 pi sum m_k tau_k^(i) / N_k)
+                                # instead of line 0 alone (Eq. decoding)
 
 
 @dataclasses.dataclass
@@ -288,7 +297,8 @@ def run(x: np.ndarray, alpha: np.ndarray, tau: np.ndarray,
       5. for each bin independently, against this iteration's residual:
          nonzero + magnitude equality, phase decode, optional on-grid check,
          projection consistency (the decoded frequency must project onto
-         this bin), amplitude a = r_0(m) exp(-j 2 pi sum m_k tau_k / N_k);
+         this bin), amplitude a = r_0(m) exp(-j 2 pi sum m_k tau_k / N_k)
+         (or its mean over the D+1 lines, params.amp_average);
          append in bin order.
     Re-detections are appended as further records (list semantics); the
     construction-subtraction sums every record. A full list stops the run
@@ -332,7 +342,12 @@ def run(x: np.ndarray, alpha: np.ndarray, tau: np.ndarray,
             if len(ra) >= params.max_k:
                 full = True
                 break
-            amp = r[0, m] * np.conj(offset_phase(f, offs[0], dims)[0])
+            if params.amp_average:
+                # each line's bin value carries its own offset's phase
+                amp = np.mean([r[i, m] * np.conj(offset_phase(f, offs[i], dims)[0])
+                               for i in range(D + 1)])
+            else:
+                amp = r[0, m] * np.conj(offset_phase(f, offs[0], dims)[0])
             rf.append(f.copy())
             ra.append(amp)
             rt.append(t)

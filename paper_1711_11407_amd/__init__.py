@@ -40,6 +40,15 @@ class CubeSpec:
     mag_rel_tol: float = 1e-3
     grid_tol: float = 1e-2
     schedule: Optional[np.ndarray] = None   # int32 [T][2][D] (alpha, tau)
+    axis_schedule: bool = False  # generated slopes e_{t mod D} (FPSSFT_FLAG_AXIS_SCHEDULE)
+    amp_average: bool = False    # amplitude averaged over the D+1 lines (FPSSFT_FLAG_AMP_AVERAGE)
+    literal_peel: bool = False   # time-domain construction-subtraction (FPSSFT_FLAG_LITERAL_PEEL)
+
+    @property
+    def flags(self) -> int:
+        return ((B.FLAG_AXIS_SCHEDULE if self.axis_schedule else 0)
+                | (B.FLAG_AMP_AVERAGE if self.amp_average else 0)
+                | (B.FLAG_LITERAL_PEEL if self.literal_peel else 0))
 
     def to_c(self):
         d = B.Desc()
@@ -55,6 +64,7 @@ class CubeSpec:
         d.zero_thresh = float(self.zero_thresh)
         d.mag_rel_tol = float(self.mag_rel_tol)
         d.grid_tol = float(self.grid_tol)
+        d.flags = self.flags
         keep = None
         if self.schedule is not None:
             keep = np.ascontiguousarray(self.schedule, dtype=np.int32)

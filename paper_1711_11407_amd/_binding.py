@@ -12,6 +12,8 @@ import os
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_lib", "libfpssft.so")
 
 MAX_D = 4
+ABI_VERSION = 2
+FLAG_AXIS_SCHEDULE, FLAG_AMP_AVERAGE, FLAG_LITERAL_PEEL = 0x1, 0x2, 0x4
 OK, INCOMPLETE, CAPACITY = 0, 1, 2
 ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_HIP, ERR_NOMEM, ERR_NO_DEVICE = -1, -2, -3, -4, -5
 
@@ -26,6 +28,7 @@ class Desc(C.Structure):
         ("zero_thresh", C.c_float),
         ("mag_rel_tol", C.c_float),
         ("grid_tol", C.c_float),
+        ("flags", C.c_uint32),
         ("schedule", C.POINTER(C.c_int32)),
     ]
 
@@ -89,6 +92,9 @@ def lib() -> C.CDLL:
             fn = getattr(L, name)
             fn.restype = res
             fn.argtypes = args
+        if L.fpssft_abi_version() != ABI_VERSION:
+            raise ImportError(f"{LIB_PATH} has ABI version {L.fpssft_abi_version()}, the binding expects "
+                              f"{ABI_VERSION}: rebuild it")
         _lib = L
     return _lib
 

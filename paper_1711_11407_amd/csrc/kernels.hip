@@ -178,7 +178,8 @@ __global__ void k_lines(const CubeDesc* __restrict__ descs, const LineItem* __re
 struct SolveLds {
   float2* bufA;    // lines; on the wave path each line's row is padded
   float2* bufB;    // the block FFT's second buffer (block path)
-  float2* P;       // [(D+1) L] peel accumulator (wave path)
+  float2* P;       // [(D+1) L] peel accumulator (wave path; block path with
+                   // the time-domain construction-subtraction)
   float2* tw;      // [L] twiddles W_L^k
   float2* rec_a;   // [rec_lds] amplitudes
   int32_t* rec_f;  // [rec_lds][D] frequency indices
@@ -194,7 +195,7 @@ struct SolveLds {
 // runs in place there) followed by the peel accumulator, the block path two
 // line buffers.
 template <int D, bool kWave>
-__device__ __forceinline__ SolveLds carve_solve_lds(char* smem, int L, int rec_lds, bool serial) {
+__device__ __forceinline__ SolveLds carve_solve_lds(char* smem, int L, int rec_lds, bool serial, bool literal) {
   SolveLds s;
   s.bufA = (float2*)smem;
   if (!kWave && serial) {
@@ -211,7 +212,13 @@ __device__ __forceinline__ SolveLds carve_solve_lds(char* smem, int L, int rec_l
     s.P = nullptr;
     s.tw = s.bufB + wave_scratch_elems((D + 1) * L);
   }
-  s.rec_a = s.tw + (!kWave && serial ? 0 : L);
+  float2* end = s.tw + (!kWave && serial ? 0 : L);
+  if (!kWave && !serial && literal) {
+    // block path, time-domain construction-subtraction: constructed spectra
+    s.P = end;
+    end += (D + 1) * L;
+  }
+  s.rec_a = end;
   s.rec_f = (int32_t*)(s.rec_a + rec_lds);
   s.rec_p = s.rec_f + rec_lds * D;
   s.rec_t = s.rec_p + rec_lds;
@@ -309,11 +316,13 @@ __device__ __forceinline__ void peel_records(const Geo<D>& g, const uint32_t (&a
 // Bin m of one iteration (r: its value on lines 0..D after the peel): the
 // nonzero and magnitude-equality tests (Sec. 2.1), the phase decode of the
 // frequency (Eq. decoding) with the on-grid check, the projection-consistency
-// check, and the amplitude r_0 exp(-j 2 pi q / L). All decisions in float32.
+// check, and the amplitude r_0 exp(-j 2 pi q / L) (with `avg`, the mean over
+// the D+1 lines of r_i exp(-j 2 pi q_i / L)). All decisions in float32.
 template <int D, bool kPow2>
 __device__ __forceinline__ bool decode_bin(const Geo<D>& g, const uint32_t (&al)[D], const uint32_t (&ta)[D],
                                            const float2 (&r)[D + 1], uint32_t m, float th0, float rho, float gtol,
-                                           const float2* tw, bool& nonzero, int (&f)[D], float2& amp) {
+                                           const float2* tw, bool avg, bool& nonzero, int (&f)[D],
+                                           float2& amp) {
   const uint32_t L = g.L;
   const float2 r0 = r[0];
   const float mag0 = sqrtf(r0.x * r0.x + r0.y * r0.y);
@@ -344,6 +353,16 @@ __device__ __forceinline__ bool decode_bin(const Geo<D>& g, const uint32_t (&al)
     }
     cand = (b == m);
     amp = c_mul(r0, tw[q]);  // r0 exp(-j 2 pi q / L)
+    if (avg) {
+      // line i's offset adds c_{i-1} m_{i-1} to the phase index
+#pragma unroll
+      for (int k = 0; k < D; ++k) {
+        uint32_t qk = q + g.c[k] * (uint32_t)f[k];
+        if (qk >= L) qk -= L;
+        amp = c_add(amp, c_mul(r[k + 1], tw[qk]));
+      }
+      amp = c_scale(amp, 1.0f / (float)(D + 1));
+    }
   }
   return cand;
 }
@@ -377,7 +396,11 @@ __device__ __forceinline__ void solve_cube(const CubeDesc& cd, const float2* __r
   // Long lines (block path only): lines transformed one at a time, twiddles
   // read from global memory (the host sends no precomputed spectra).
   const bool serial = !(kWave && kPow2) && cd.serial != 0;
-  SolveLds s = carve_solve_lds<D, kWave>(smem, (int)L, kRecLds ? cd.rec_lds : 0, serial);
+  // Time-domain construction-subtraction (block path; the host sends such
+  // cubes nowhere else) and line-averaged amplitudes.
+  const bool literal = !(kWave && kPow2) && !serial && (cd.flags & FPS_LITERAL_PEEL) != 0;
+  const bool avg = (cd.flags & FPS_AMP_AVERAGE) != 0;
+  SolveLds s = carve_solve_lds<D, kWave>(smem, (int)L, kRecLds ? cd.rec_lds : 0, serial, literal);
   if (!serial)
     for (uint32_t e = tid; e < L; e += B) s.tw[e] = ld_g(twall, cd.tw_off + e);
   const float2* tw = serial ? twall + cd.tw_off : s.tw;
@@ -485,11 +508,28 @@ __device__ __forceinline__ void solve_cube(const CubeDesc& cd, const float2* __r
         gather_lines<D, kPow2>(s.bufA, x, g, at, 1, inv_L);
       }
       lds_barrier();
+      if (literal) {
+        // Construction-subtraction as stated in Sec. 2.2: the records' line
+        // spectra (Eq. freqSum) go through an unnormalised inverse DFT, read
+        // as the forward DFT at index (L - l) mod L, and are subtracted from
+        // the samples (held divided by L, hence the constructed ones too).
+        for (uint32_t e = tid; e < (D + 1) * L; e += B) s.P[e] = make_float2(0.f, 0.f);
+        lds_barrier();
+        peel_records<D, kPow2, kRecLds>(g, al, ta, s, out, tw, tid, B, kc, s.P, (int)L, 1.0f);
+        lds_barrier();
+        const float2* R = block_fft<kPow2>(s.P, s.bufB, D + 1, (int)L, cd.nstages, cd.radix, tw);
+        for (int i = 0; i <= D; ++i)
+          for (uint32_t l = tid; l < L; l += B) {
+            const uint32_t lr = l ? L - l : 0u;
+            s.bufA[i * L + l] = c_sub(s.bufA[i * L + l], c_scale(R[i * L + lr], inv_L));
+          }
+        lds_barrier();
+      }
       S = precomputed ? s.bufA : block_fft<kPow2>(s.bufA, s.bufB, D + 1, (int)L, cd.nstages, cd.radix, tw);
       if (use_pf && t + 1 < T)
         prefetch_issue<D, kPow2>(pf, g, x, at + 2 * D, pre + (int64_t)(t + 1) * (D + 1) * L, t + 1 < pre_count);
     }
-    if (!conc) {
+    if (!conc && !literal) {
       peel_records<D, kPow2, kRecLds>(g, al, ta, s, out, tw, tid, B, kc, S, sstr, -1.0f);
       lds_barrier();
     }
@@ -514,7 +554,7 @@ __device__ __forceinline__ void solve_cube(const CubeDesc& cd, const float2* __r
             s.P[i * L + m] = make_float2(0.f, 0.f);
           }
         }
-        cand = decode_bin<D, kPow2>(g, al, ta, r, m, th0, rho, gtol, tw, nonzero, f, amp);
+        cand = decode_bin<D, kPow2>(g, al, ta, r, m, th0, rho, gtol, tw, avg, nonzero, f, amp);
       }
       int slot = -1;
       const unsigned long long bal = __ballot(cand ? 1 : 0);

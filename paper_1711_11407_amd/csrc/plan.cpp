@@ -78,6 +78,8 @@ fpssft_status validate(const fpssft_desc* d, int32_t* L_out, int32_t* T_out) {
   if (!std::isfinite(d->mag_rel_tol) || d->mag_rel_tol < 0.f) return FPSSFT_ERR_INVALID_ARG;
   if (!std::isfinite(d->grid_tol)) return FPSSFT_ERR_INVALID_ARG;
   if (d->schedule && d->max_iters == 0) return FPSSFT_ERR_INVALID_ARG;
+  if (d->flags & ~(FPSSFT_FLAG_AXIS_SCHEDULE | FPSSFT_FLAG_AMP_AVERAGE | FPSSFT_FLAG_LITERAL_PEEL))
+    return FPSSFT_ERR_INVALID_ARG;
   const int64_t L = lcm_dims(d->dims, d->ndim, kMaxL);
   if (L < 0) return FPSSFT_ERR_UNSUPPORTED;
   for (int k = 0; k < d->ndim; ++k)
@@ -100,16 +102,22 @@ fpssft_status validate(const fpssft_desc* d, int32_t* L_out, int32_t* T_out) {
 
 void generate_schedule(const fpssft_desc* d, int32_t L, int32_t T, int32_t* at) {
   const int D = d->ndim;
+  const bool axis = (d->flags & FPSSFT_FLAG_AXIS_SCHEDULE) != 0;
   uint64_t ctr = 0;
   for (int32_t t = 0; t < T; ++t) {
     int32_t* row = at + (int64_t)t * 2 * D;
-    for (;;) {
-      int64_t g = 0;
-      for (int k = 0; k < D; ++k) {
-        row[k] = (int32_t)draw_below(splitmix64(d->seed, ctr++), (uint32_t)d->dims[k]);
-        g = gcd64(g, (int64_t)(L / d->dims[k]) * row[k]);
+    if (axis) {
+      // alpha = e_{t mod D} (reduced mod N_k for a side of 1)
+      for (int k = 0; k < D; ++k) row[k] = (k == t % D ? 1 : 0) % d->dims[k];
+    } else {
+      for (;;) {
+        int64_t g = 0;
+        for (int k = 0; k < D; ++k) {
+          row[k] = (int32_t)draw_below(splitmix64(d->seed, ctr++), (uint32_t)d->dims[k]);
+          g = gcd64(g, (int64_t)(L / d->dims[k]) * row[k]);
+        }
+        if (g == 1) break;
       }
-      if (g == 1) break;
     }
     for (int k = 0; k < D; ++k)
       row[D + k] = (int32_t)draw_below(splitmix64(d->seed, ctr++), (uint32_t)d->dims[k]);
@@ -262,7 +270,10 @@ struct fpssft_plan_st {
 namespace {
 
 // Cubes the one-wave-per-line path can take (power-of-two 64 <= L <= 512).
-bool wave_eligible(const CubeDesc& c) { return c.Lmask >= 0 && c.L >= 64 && c.L <= 512; }
+// The time-domain construction-subtraction runs on the block path only.
+bool wave_eligible(const CubeDesc& c) {
+  return c.Lmask >= 0 && c.L >= 64 && c.L <= 512 && !(c.flags & FPS_LITERAL_PEEL);
+}
 
 size_t solve_lds_bytes(const CubeDesc& c, int rec_lds) {
   if (c.serial) {
@@ -275,8 +286,10 @@ size_t solve_lds_bytes(const CubeDesc& c, int rec_lds) {
   // take 2 (D+1) L + (D+1) L / 8 values), twiddles; per record the
   // amplitude, D frequency indices, output position, iteration and bin;
   // the exchange words.
+  // The time-domain construction-subtraction accumulates the constructed
+  // spectra in a further (D+1) L values.
   const size_t lines = (size_t)(c.D + 1) * c.L;
-  size_t b = (2 * lines + lines / 8 + c.L) * sizeof(float2);
+  size_t b = (2 * lines + lines / 8 + c.L + ((c.flags & FPS_LITERAL_PEEL) ? lines : 0)) * sizeof(float2);
   b += (size_t)rec_lds * (sizeof(float2) + (c.D + 3) * sizeof(int32_t));
   b += 64 * sizeof(int);
   return b;
@@ -380,6 +393,7 @@ fpssft_status build_plan(const fpssft_desc* descs, int32_t batch, const fpssft_t
     cd.zero_thresh = d.zero_thresh;
     cd.mag_rel_tol = d.mag_rel_tol;
     cd.grid_tol = d.grid_tol;
+    cd.flags = d.flags;
     cd.sched_off = (int32_t)p->sched.size();
     if ((int64_t)p->sched.size() + (int64_t)T * 2 * d.ndim >= (int64_t(1) << 31)) return FPSSFT_ERR_UNSUPPORTED;
     p->sched.resize(p->sched.size() + (size_t)T * 2 * d.ndim);
@@ -403,7 +417,9 @@ fpssft_status build_plan(const fpssft_desc* descs, int32_t batch, const fpssft_t
     // twiddles in LDS are transformed one at a time (no precomputed chunk).
     cd.serial = 0;
     if (!wave_eligible(cd) && solve_lds_bytes(cd, 0) > p->lds_max) cd.serial = 1;
-    const int32_t pre_T = cd.serial ? 0 : std::min(T, tn.chunk_iters);
+    if (cd.serial && (cd.flags & FPS_LITERAL_PEEL)) return FPSSFT_ERR_UNSUPPORTED;
+    // the time-domain construction-subtraction needs the samples themselves
+    const int32_t pre_T = (cd.serial || (cd.flags & FPS_LITERAL_PEEL)) ? 0 : std::min(T, tn.chunk_iters);
     max_pre = std::max<int64_t>(max_pre, (int64_t)pre_T * (d.ndim + 1) * L);
     p->max_N = std::max(p->max_N, cd.N);
     if (solve_lds_bytes(cd, 0) > p->lds_max || lines_single_lds_bytes(cd) > p->lds_max)
@@ -652,7 +668,7 @@ fpssft_status fpssft_execute(fpssft_plan_t p, int32_t cube, const void* x, const
   const CubeDesc& cd = p->descs[cube];
   const fpssft::KernelKey key = key_of(p, cube);
   const Group& g = p->groups[p->group_of[cube]];
-  const int pre = cd.serial ? 0 : std::min(cd.T, p->tune.chunk_iters);
+  const int pre = (cd.serial || (cd.flags & FPS_LITERAL_PEEL)) ? 0 : std::min(cd.T, p->tune.chunk_iters);
   if (pre > 0) {
     HIP_TRY(fpssft::launch_lines_single(p->ctx, key, cube, (const float2*)x, 0, pre, p->d_pre, cd.L,
                                         lines_single_lds_bytes(cd), p->tune.lines_threads, st));
@@ -732,7 +748,8 @@ fpssft_status fpssft_amp_backward(fpssft_plan_t p, int32_t cube, const fpssft_ou
                                   void* grad_x, void* stream) {
   if (!p || cube < 0 || cube >= p->B || !check_out(fwd) || !grad_amps || !grad_x) return FPSSFT_ERR_INVALID_ARG;
   const CubeDesc& cd = p->descs[cube];
-  if (bwd_lds_bytes(cd) > p->lds_max) return FPSSFT_ERR_UNSUPPORTED;
+  // the adjoint follows the line-0 amplitude of Eq. decoding
+  if (bwd_lds_bytes(cd) > p->lds_max || (cd.flags & FPS_AMP_AVERAGE)) return FPSSFT_ERR_UNSUPPORTED;
   hipStream_t st = (hipStream_t)stream;
   HIP_TRY(fpssft::launch_zero_single((float2*)grad_x, cd.N, st));
   HIP_TRY(fpssft::launch_backward_single(p->ctx, key_of(p, cube), cube, to_ptrs(*fwd), (const float2*)grad_amps,
@@ -747,7 +764,8 @@ fpssft_status fpssft_amp_backward_batched(fpssft_plan_t p, const fpssft_out* fwd
   std::vector<int64_t> lens(p->B);
   for (int c = 0; c < p->B; ++c) {
     if (!check_out(&fwds[c]) || !grad_amps[c] || !grad_xs[c]) return FPSSFT_ERR_INVALID_ARG;
-    if (bwd_lds_bytes(p->descs[c]) > p->lds_max) return FPSSFT_ERR_UNSUPPORTED;
+    if (bwd_lds_bytes(p->descs[c]) > p->lds_max || (p->descs[c].flags & FPS_AMP_AVERAGE))
+      return FPSSFT_ERR_UNSUPPORTED;
     op[c] = to_ptrs(fwds[c]);
     lens[c] = p->descs[c].N;
   }

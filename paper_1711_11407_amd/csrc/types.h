@@ -4,6 +4,11 @@
 
 #define FPSSFT_MAX_STAGES 24
 
+// Method variants (the same bits as FPSSFT_FLAG_* of the C ABI).
+#define FPS_AXIS_SCHEDULE 0x1u
+#define FPS_AMP_AVERAGE 0x2u
+#define FPS_LITERAL_PEEL 0x4u
+
 // Everything a kernel needs to know about one cube. Built on the host,
 // uploaded once per plan, read through scalar loads on the device.
 struct CubeDesc {
@@ -28,6 +33,8 @@ struct CubeDesc {
   int32_t rec_lds;           // records kept in LDS (capacity), 0: global
   int32_t serial;            // long lines: transformed one at a time through a
                              // one-line scratch, twiddles read from global memory
+  uint32_t flags;            // FPSSFT_FLAG_* of the description
+  int32_t pad1;
   int64_t spec_off;          // element offset in the packed spectra buffer
 };
 

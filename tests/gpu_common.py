@@ -31,13 +31,13 @@ def oracle_for(plan, cube_idx, x, spec):
     generator unless the schedule was given explicitly)."""
     sched = plan.schedule(cube_idx)
     if spec.schedule is None:
-        al, ta = O.schedule(spec.dims, plan.max_iters(cube_idx), spec.seed)
+        al, ta = O.schedule(spec.dims, plan.max_iters(cube_idx), spec.seed, axis=spec.axis_schedule)
         assert (sched[:, 0] == al).all() and (sched[:, 1] == ta).all()
     else:
         al, ta = sched[:, 0].astype(np.int64), sched[:, 1].astype(np.int64)
     params = O.Params(zero_thresh=spec.zero_thresh, mag_rel_tol=spec.mag_rel_tol,
                       grid_tol=spec.grid_tol, max_iters=plan.max_iters(cube_idx),
-                      max_k=spec.max_k)
+                      max_k=spec.max_k, amp_average=spec.amp_average)
     return O.run(x, al, ta, params), al, ta
 
 

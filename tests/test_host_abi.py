@@ -37,7 +37,7 @@ def test_library_exports_every_declared_symbol(F):
     for n in names:
         assert hasattr(lib, n), n
     assert {s[0] for s in _binding.SIGNATURES} == set(names)
-    assert lib.fpssft_abi_version() == 1
+    assert lib.fpssft_abi_version() == 2
 
 
 def test_validate_line_length_and_budget(F):
@@ -78,6 +78,23 @@ def test_schedule_matches_oracle_generator(F, dims, seed):
     al, ta = O.schedule(dims, T, seed)
     np.testing.assert_array_equal(got[:, 0, :], al)
     np.testing.assert_array_equal(got[:, 1, :], ta)
+
+
+@pytest.mark.parametrize("dims", [(64, 64), (16, 24), (4, 6, 10), (32,), (1, 8), (3, 5, 7, 2)])
+def test_axis_schedule_matches_oracle_generator(F, dims):
+    got = F.schedule_generate(F.CubeSpec(dims, seed=3, axis_schedule=True), 30)
+    al, ta = O.schedule(dims, 30, 3, axis=True)
+    np.testing.assert_array_equal(got[:, 0, :], al)
+    np.testing.assert_array_equal(got[:, 1, :], ta)
+
+
+def test_unknown_flag_rejected(F):
+    import ctypes as C
+    from paper_1711_11407_amd import _binding as B
+    d, _keep = F.CubeSpec((8, 8), amp_average=True, literal_peel=True, axis_schedule=True).to_c()
+    assert d.flags == 0x7 and B.lib().fpssft_validate(C.byref(d), None, None) == 0
+    d.flags = 0x8
+    assert B.lib().fpssft_validate(C.byref(d), None, None) == -1
 
 
 def test_workload_schedules_match(F):
