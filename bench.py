@@ -3,8 +3,9 @@
 Workload (one step): the batched workload of 1024 independent 2-D complex64
 cubes, sides drawn iid from {64, 128, 256, 512}, K ~ U{10..300} on-grid
 sinusoids of unit magnitude and random phase, noiseless (seed 4), recovered
-by one persistent launch replayed from a HIP graph. Inputs are resident in
-HBM before the timed region.
+by one persistent launch (launched directly on the stream or replayed from
+a HIP graph, as the tuned launch shapes say). Inputs are resident in HBM
+before the timed region.
 
 Printed as one JSON line:
   value         batched sparse transforms/s (1024 / step time)
@@ -35,7 +36,7 @@ HBM_PEAK_GBS = 8000.0
 METRIC = "sparse transforms/sec (batched vs plain) at exact support; line-FFT HBM GB/s"
 WORKLOAD = ("batched: 1024 independent 2-D complex64 cubes, N0,N1 iid from {64,128,256,512}, "
             "K~U{10..300} on-grid sinusoids, |a|=1, random phase, noiseless, seed 4; "
-            "one persistent launch replayed from a HIP graph")
+            "one persistent solve launch per step")
 KERNEL_SOURCES = ["paper_1711_11407_amd/csrc/kernels.hip", "paper_1711_11407_amd/csrc/device.h",
                   "paper_1711_11407_amd/csrc/types.h"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")

@@ -133,13 +133,18 @@ typedef struct {
  *                 in parallel before its sequential decode (>= 0)
  *  lines_wg       consecutive iterations per work item of the persistent
  *                 line gather + FFT kernel (>= 1)
- *  lines_threads  threads per work-group of that kernel (64..1024) */
+ *  lines_threads  threads per work-group of that kernel (64..1024)
+ *  direct_launch  fpssft_execute_batched: 0 replays one HIP graph holding
+ *                 the persistent solve launches (default), 1 launches them
+ *                 on the stream directly (no graph; the launches may then be
+ *                 captured into the caller's own graph) */
 typedef struct {
   int32_t block_threads;
   int32_t max_radix;
   int32_t chunk_iters;
   int32_t lines_wg;
   int32_t lines_threads;
+  int32_t direct_launch;
 } fpssft_tuning;
 
 typedef struct fpssft_plan_st* fpssft_plan_t;
@@ -211,8 +216,9 @@ int64_t fpssft_plan_spectra_elems(fpssft_plan_t plan);
 fpssft_status fpssft_execute(fpssft_plan_t plan, int32_t cube, const void* x,
                              const fpssft_out* out, void* stream);
 
-/* All cubes of the plan in one persistent launch (work-groups take cubes
- * from a device queue, shortest lines first), replayed from a HIP graph. xs: host
+/* All cubes of the plan in one persistent launch per kernel instantiation
+ * (work-groups take cubes from a device queue, shortest lines first),
+ * replayed from a HIP graph or launched directly (fpssft_tuning). xs: host
  * array of `batch` device cube pointers; outs: host array of `batch` output
  * structs. Results equal fpssft_execute's cube by cube. */
 fpssft_status fpssft_execute_batched(fpssft_plan_t plan, const void* const* xs,

@@ -148,6 +148,7 @@ class Plan:
             tn.chunk_iters = int(tuning.get("chunk_iters", -1))
             tn.lines_wg = int(tuning.get("lines_wg", 0))
             tn.lines_threads = int(tuning.get("lines_threads", 0))
+            tn.direct_launch = int(tuning.get("direct_launch", 0))
         h = C.c_void_p()
         B.check(B.lib().fpssft_plan_create(descs, len(self.specs), C.byref(tn) if tn else None, C.byref(h)),
                 "plan_create")

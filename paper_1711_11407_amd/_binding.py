@@ -50,6 +50,7 @@ class Tuning(C.Structure):
         ("chunk_iters", C.c_int32),
         ("lines_wg", C.c_int32),
         ("lines_threads", C.c_int32),
+        ("direct_launch", C.c_int32),
     ]
 
 

@@ -186,93 +186,109 @@ __device__ __forceinline__ void dft_small(float2* v) {
   if constexpr (E == 16) dft16(v);
 }
 
-// Orders the LDS accesses of one wave (its lanes exchange data through a
-// wave-private scratch; no other wave is involved).
-__device__ __forceinline__ void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+// ---------------------------------------------------------------------------
+// Register-only wave FFT: one wave transforms one line of L = 64 E points
+// (E = 1, 2, 4, 8), forward and unnormalised, without LDS scratch. On entry
+// lane q holds v[e] = x[e + E q]. Cooley-Tukey with n = e + E q and
+// k = k2 + 64 k1:
+//   1. for each e, the 64-point DFT over the lanes q, radix 2 with
+//      decimation in frequency: six butterfly stages exchange values between
+//      lanes q and q ^ h (h = 32, 16: permlane swaps; h = 8, 4, 2, 1: DPP
+//      row rotations and quad permutations), leaving bin k2 = bitrev6(q) in
+//      lane q;
+//   2. twiddles W_L^{e k2};
+//   3. the E-point DFT over e in registers gives X[k2 + 64 k1] in v[k1].
+// store(k, X[k]) receives the result; each store instruction of the wave
+// covers 64 consecutive bins in bit-reversed lane order. tw: W_L^k, k < L
+// (W_64^j = W_L^{E j}).
+// ---------------------------------------------------------------------------
+
+// Values of lanes q and q ^ H (H = 32, 16) as (lower, upper) of the pair.
+template <int H>
+__device__ __forceinline__ void lane_pair_swap(float v, float& lo, float& hi) {
+  const unsigned u = __float_as_uint(v);
+  if constexpr (H == 32) {
+    const auto r = __builtin_amdgcn_permlane32_swap(u, u, false, false);
+    lo = __uint_as_float(r[0]);
+    hi = __uint_as_float(r[1]);
+  } else {
+    static_assert(H == 16, "permlane swaps cover lane distances 32 and 16");
+    const auto r = __builtin_amdgcn_permlane16_swap(u, u, false, false);
+    lo = __uint_as_float(r[0]);
+    hi = __uint_as_float(r[1]);
+  }
 }
 
-// ---------------------------------------------------------------------------
-// Wave FFT: one wave transforms one line of L = 64 E points (E = 1..16, a
-// power of two), forward and unnormalised. On entry lane q holds
-// v[e] = x[q + 64 e]. Cooley-Tukey with L = E x 64 (n = q + 64 e,
-// k = k1 + E k2): an E-point DFT over e in registers, twiddles W_L^{q k1},
-// then the 64-point DFT over q as 8 x 8 (q = 8 a + b, k2 = c + 8 d) through
-// `scr`, a wave-private LDS scratch of 72 E values (wave_scratch_elems).
-// store(k, X[k]) receives the result; each store instruction of the wave
-// covers 64 consecutive bins. tw: W_L^k, k < L. For E <= 8 every scratch
-// read of the wave precedes every result store, so the result may overwrite
-// the scratch (scr is not restrict-qualified for that reason).
-//
-// Scratch layout: row k1 holds q = 8 x + y at wave_slot = 72 k1 + 9 x + y.
-// Every access of the 8 x 8 steps is then a per-lane base plus an immediate
-// offset, and none meets more than a 2-way LDS bank conflict (64-wide rows
-// reach 8-way on the transposed reads). Each stage's twiddle reads are
-// issued together, ahead of the arithmetic that uses them.
-// ---------------------------------------------------------------------------
-__host__ __device__ constexpr int wave_scratch_elems(int L) { return L + L / 8; }
+// Value of lane q ^ H for H = 8, 4, 2, 1 (within a row of 16 lanes).
+template <int H>
+__device__ __forceinline__ float lane_partner_dpp(float v, int lane) {
+  const int u = __float_as_int(v);
+  int p;
+  if constexpr (H == 8) {
+    p = __builtin_amdgcn_update_dpp(0, u, 0x128, 0xF, 0xF, false);  // row_ror:8
+  } else if constexpr (H == 4) {
+    const int up = __builtin_amdgcn_update_dpp(0, u, 0x12C, 0xF, 0xF, false);  // row_ror:12: lane + 4
+    const int dn = __builtin_amdgcn_update_dpp(0, u, 0x124, 0xF, 0xF, false);  // row_ror:4: lane - 4
+    p = (lane & 4) ? dn : up;
+  } else if constexpr (H == 2) {
+    p = __builtin_amdgcn_update_dpp(0, u, 0x4E, 0xF, 0xF, false);  // quad_perm 2,3,0,1
+  } else {
+    static_assert(H == 1, "DPP partners cover lane distances 8, 4, 2, 1");
+    p = __builtin_amdgcn_update_dpp(0, u, 0xB1, 0xF, 0xF, false);  // quad_perm 1,0,3,2
+  }
+  return __int_as_float(p);
+}
 
-__device__ __forceinline__ int wave_slot(int k1, int q) { return k1 * 72 + 9 * (q >> 3) + (q & 7); }
+// One decimation-in-frequency stage over lane bit H: the lower lane of a
+// pair keeps lo + hi, the upper lane (lo - hi) W_{2H}^{q mod H}; w is that
+// twiddle in upper lanes and 1 in lower ones, sgn -1 in upper lanes.
+template <int H>
+__device__ __forceinline__ float2 lane_butterfly(float2 v, float sgn, float2 w, int lane) {
+  float2 t;
+  if constexpr (H >= 16) {
+    float lx, hx, ly, hy;
+    lane_pair_swap<H>(v.x, lx, hx);
+    lane_pair_swap<H>(v.y, ly, hy);
+    t = make_float2(fmaf(sgn, hx, lx), fmaf(sgn, hy, ly));
+  } else {
+    // partner p: lower lane p + v = lo + hi, upper lane p - v = lo - hi
+    const float2 p = make_float2(lane_partner_dpp<H>(v.x, lane), lane_partner_dpp<H>(v.y, lane));
+    t = make_float2(fmaf(sgn, v.x, p.x), fmaf(sgn, v.y, p.y));
+  }
+  if constexpr (H > 1) t = c_mul(t, w);
+  return t;
+}
 
 template <int E, class Store>
-__device__ __forceinline__ void wave_fft(float2 (&v)[E], float2* scr, const float2* __restrict__ tw, Store&& store) {
+__device__ __forceinline__ void wave_fft_lanes(float2 (&v)[E], const float2* __restrict__ tw, Store&& store) {
   const int lane = threadIdx.x & 63;
+  const int k2 = (int)(__builtin_bitreverse32((unsigned)lane) >> 26);
+  // Stage twiddles W_64^{(q mod h) 32/h} (upper lanes; W^0 = 1 below) and
+  // the W_L^{e k2} of step 2, read together ahead of the arithmetic.
+  float2 ws[5];
+#pragma unroll
+  for (int s = 0; s < 5; ++s) {
+    const int h = 32 >> s;
+    ws[s] = tw[(lane & h) ? E * (lane & (h - 1)) * (32 / h) : 0];
+  }
+  float2 w2[E];
+#pragma unroll
+  for (int e = 1; e < E; ++e) w2[e] = tw[e * k2];
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    float2 a = v[e];
+    a = lane_butterfly<32>(a, (lane & 32) ? -1.f : 1.f, ws[0], lane);
+    a = lane_butterfly<16>(a, (lane & 16) ? -1.f : 1.f, ws[1], lane);
+    a = lane_butterfly<8>(a, (lane & 8) ? -1.f : 1.f, ws[2], lane);
+    a = lane_butterfly<4>(a, (lane & 4) ? -1.f : 1.f, ws[3], lane);
+    a = lane_butterfly<2>(a, (lane & 2) ? -1.f : 1.f, ws[4], lane);
+    a = lane_butterfly<1>(a, (lane & 1) ? -1.f : 1.f, make_float2(1.f, 0.f), lane);
+    v[e] = e ? c_mul(a, w2[e]) : a;
+  }
   dft_small<E>(v);
-  if constexpr (E > 1) {
-    float2 w[E];
 #pragma unroll
-    for (int k1 = 1; k1 < E; ++k1) w[k1] = tw[lane * k1];
-    __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-    for (int k1 = 1; k1 < E; ++k1) v[k1] = c_mul(v[k1], w[k1]);
-  }
-#pragma unroll
-  for (int k1 = 0; k1 < E; ++k1) scr[wave_slot(k1, lane)] = v[k1];
-  wave_lds_sync();
-  constexpr int NJ = (8 * E + 63) / 64;
-  float2 u[NJ][8];
-#pragma unroll
-  for (int j = 0; j < NJ; ++j) {
-    const int p = lane + 64 * j;
-    if (p < 8 * E) {
-      const int k1 = p >> 3, b = p & 7;
-      float2 w[8];
-#pragma unroll
-      for (int a = 0; a < 8; ++a) u[j][a] = scr[wave_slot(k1, 8 * a + b)];
-#pragma unroll
-      for (int c = 1; c < 8; ++c) w[c] = tw[E * b * c];
-      __builtin_amdgcn_sched_barrier(0);
-      dft8(u[j]);
-#pragma unroll
-      for (int c = 1; c < 8; ++c) u[j][c] = c_mul(u[j][c], w[c]);
-    }
-  }
-  wave_lds_sync();
-#pragma unroll
-  for (int j = 0; j < NJ; ++j) {
-    const int p = lane + 64 * j;
-    if (p < 8 * E) {
-      const int k1 = p >> 3, b = p & 7;
-#pragma unroll
-      for (int c = 0; c < 8; ++c) scr[wave_slot(k1, 8 * c + b)] = u[j][c];
-    }
-  }
-  wave_lds_sync();
-#pragma unroll
-  for (int j = 0; j < NJ; ++j) {
-    const int p = lane + 64 * j;
-    if (p < 8 * E) {
-      const int k1 = p >> 3, c = p & 7;
-#pragma unroll
-      for (int b = 0; b < 8; ++b) u[j][b] = scr[wave_slot(k1, 8 * c + b)];
-      dft8(u[j]);
-#pragma unroll
-      for (int d = 0; d < 8; ++d) store(k1 + E * (c + 8 * d), u[j][d]);
-    }
-  }
-  wave_lds_sync();
+  for (int k1 = 0; k1 < E; ++k1) store(k2 + 64 * k1, v[k1]);
 }
 
 // ---------------------------------------------------------------------------

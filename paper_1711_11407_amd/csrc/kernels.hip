@@ -190,10 +190,9 @@ struct SolveLds {
   int* cnt;        // [1] length of the LDS record list
 };
 
-// Both layouts take 2 (D+1) L + (D+1) L / 8 + L values before the records:
-// the wave path keeps each line in a row of wave_scratch_elems(L) (its FFT
-// runs in place there) followed by the peel accumulator, the block path two
-// line buffers.
+// Both layouts take 2 (D+1) L + L values before the records: the wave path
+// the D+1 spectra (each wave's transform writes its row) and the peel
+// accumulator, the block path two line buffers; then the twiddles.
 template <int D, bool kWave>
 __device__ __forceinline__ SolveLds carve_solve_lds(char* smem, int L, int rec_lds, bool serial, bool literal) {
   SolveLds s;
@@ -205,12 +204,12 @@ __device__ __forceinline__ SolveLds carve_solve_lds(char* smem, int L, int rec_l
     s.tw = s.bufB + L;
   } else if constexpr (kWave) {
     s.bufB = nullptr;
-    s.P = s.bufA + (D + 1) * wave_scratch_elems(L);
+    s.P = s.bufA + (D + 1) * L;
     s.tw = s.P + (D + 1) * L;
   } else {
     s.bufB = s.bufA + (D + 1) * L;
     s.P = nullptr;
-    s.tw = s.bufB + wave_scratch_elems((D + 1) * L);
+    s.tw = s.bufB + (D + 1) * L;
   }
   float2* end = s.tw + (!kWave && serial ? 0 : L);
   if (!kWave && !serial && literal) {
@@ -257,7 +256,8 @@ __device__ __forceinline__ void wave_prefetch(float2 (&pf)[kEMax], int E, const 
 #pragma unroll
   for (int e = 0; e < kEMax; ++e) {
     if (e < E) {
-      const uint32_t l = lane + 64 * e;
+      // the wave transform takes sample e + E q in register e of lane q
+      const uint32_t l = (uint32_t)E * lane + e;
       int64_t flat = 0;
 #pragma unroll
       for (int k = 0; k < D; ++k) flat += (int64_t)umod<kPow2>(al[k] * l + ta[k], g.dims[k]) * g.stride[k];
@@ -267,14 +267,11 @@ __device__ __forceinline__ void wave_prefetch(float2 (&pf)[kEMax], int E, const 
 }
 
 template <int E>
-__device__ __forceinline__ void wave_fft_to_lds(const float2 (&in)[kEMax], float2* scr, const float2* tw,
-                                                float2* dst) {
-  // dst may be scr (in place), which needs one 8 x 8 block per lane
-  static_assert(E <= 8, "in-place wave FFT needs L <= 512");
+__device__ __forceinline__ void wave_fft_to_lds(const float2 (&in)[kEMax], const float2* tw, float2* dst) {
   float2 v[E];
 #pragma unroll
   for (int e = 0; e < E; ++e) v[e] = in[e];
-  wave_fft<E>(v, scr, tw, [&](int k, float2 val) { dst[k] = val; });
+  wave_fft_lanes<E>(v, tw, [&](int k, float2 val) { dst[k] = val; });
 }
 
 // Peel (construction-subtraction, Sec. 2.2): the projection of record j
@@ -415,8 +412,6 @@ __device__ __forceinline__ void solve_cube(const CubeDesc& cd, const float2* __r
   constexpr bool wave_path = kWave && kPow2;
   // Peel concurrently with the transforms when some waves have no line.
   const bool conc = kRecLds && wave_path && nw > D + 1;
-  // distance between the lines of the spectra
-  const int sstr = wave_path ? wave_scratch_elems((int)L) : (int)L;
   if (tid == 0) s.cnt[0] = 0;
   if constexpr (wave_path)
     for (uint32_t e = tid; e < (D + 1) * L; e += B) s.P[e] = make_float2(0.f, 0.f);
@@ -458,20 +453,17 @@ __device__ __forceinline__ void solve_cube(const CubeDesc& cd, const float2* __r
           cur[e] = c_scale(pfw[e], sc);
           __asm__ volatile("" : "+v"(cur[e].x), "+v"(cur[e].y));
         }
-        // In place: the transform's last reads of its scratch precede its
-        // result stores in this wave's program order, and LDS serves one
-        // wave's accesses in order.
-        float2* dst = s.bufA + wv * wave_scratch_elems((int)L);
+        float2* dst = s.bufA + wv * L;
         if (precomputed) {
 #pragma unroll
           for (int e = 0; e < kEMax; ++e)
             if (e < E) dst[lane + 64 * e] = cur[e];
         } else {
           switch (E) {
-            case 1: wave_fft_to_lds<1>(cur, dst, tw, dst); break;
-            case 2: wave_fft_to_lds<2>(cur, dst, tw, dst); break;
-            case 4: wave_fft_to_lds<4>(cur, dst, tw, dst); break;
-            default: wave_fft_to_lds<8>(cur, dst, tw, dst); break;
+            case 1: wave_fft_to_lds<1>(cur, tw, dst); break;
+            case 2: wave_fft_to_lds<2>(cur, tw, dst); break;
+            case 4: wave_fft_to_lds<4>(cur, tw, dst); break;
+            default: wave_fft_to_lds<8>(cur, tw, dst); break;
           }
         }
         // The next iteration's gathers are issued after the transform: in
@@ -530,7 +522,7 @@ __device__ __forceinline__ void solve_cube(const CubeDesc& cd, const float2* __r
         prefetch_issue<D, kPow2>(pf, g, x, at + 2 * D, pre + (int64_t)(t + 1) * (D + 1) * L, t + 1 < pre_count);
     }
     if (!conc && !literal) {
-      peel_records<D, kPow2, kRecLds>(g, al, ta, s, out, tw, tid, B, kc, S, sstr, -1.0f);
+      peel_records<D, kPow2, kRecLds>(g, al, ta, s, out, tw, tid, B, kc, S, (int)L, -1.0f);
       lds_barrier();
     }
 
@@ -546,7 +538,7 @@ __device__ __forceinline__ void solve_cube(const CubeDesc& cd, const float2* __r
       if (m < L) {
         float2 r[D + 1];
 #pragma unroll
-        for (int i = 0; i <= D; ++i) r[i] = S[i * sstr + m];
+        for (int i = 0; i <= D; ++i) r[i] = S[i * L + m];
         if (conc) {
 #pragma unroll
           for (int i = 0; i <= D; ++i) {

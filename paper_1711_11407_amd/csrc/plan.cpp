@@ -282,14 +282,13 @@ size_t solve_lds_bytes(const CubeDesc& c, int rec_lds) {
     b += (size_t)rec_lds * (sizeof(float2) + (c.D + 3) * sizeof(int32_t));
     return b + 64 * sizeof(int);
   }
-  // Lines, second buffer or padded rows plus peel accumulator (both layouts
-  // take 2 (D+1) L + (D+1) L / 8 values), twiddles; per record the
-  // amplitude, D frequency indices, output position, iteration and bin;
-  // the exchange words.
-  // The time-domain construction-subtraction accumulates the constructed
-  // spectra in a further (D+1) L values.
+  // Lines, and a second buffer or the peel accumulator (2 (D+1) L values),
+  // twiddles; per record the amplitude, D frequency indices, output
+  // position, iteration and bin; the exchange words. The time-domain
+  // construction-subtraction accumulates the constructed spectra in a
+  // further (D+1) L values.
   const size_t lines = (size_t)(c.D + 1) * c.L;
-  size_t b = (2 * lines + lines / 8 + c.L + ((c.flags & FPS_LITERAL_PEEL) ? lines : 0)) * sizeof(float2);
+  size_t b = (2 * lines + c.L + ((c.flags & FPS_LITERAL_PEEL) ? lines : 0)) * sizeof(float2);
   b += (size_t)rec_lds * (sizeof(float2) + (c.D + 3) * sizeof(int32_t));
   b += 64 * sizeof(int);
   return b;
@@ -348,13 +347,14 @@ fpssft_status build_plan(const fpssft_desc* descs, int32_t batch, const fpssft_t
   if (v <= 2048) return FPSSFT_ERR_UNSUPPORTED;
   p->lds_max = (size_t)v - 1024;
   p->B = batch;
-  fpssft_tuning tn{256, 8, 8, 4, 256};
+  fpssft_tuning tn{256, 8, 8, 4, 256, 0};
   if (tuning) {
     if (tuning->block_threads) tn.block_threads = tuning->block_threads;
     if (tuning->max_radix) tn.max_radix = tuning->max_radix;
     if (tuning->chunk_iters >= 0) tn.chunk_iters = tuning->chunk_iters;
     if (tuning->lines_wg) tn.lines_wg = tuning->lines_wg;
     if (tuning->lines_threads) tn.lines_threads = tuning->lines_threads;
+    tn.direct_launch = tuning->direct_launch != 0;
   }
   if (tn.block_threads < 64 || tn.block_threads > 512 || tn.block_threads % 64) return FPSSFT_ERR_INVALID_ARG;
   if (tn.lines_threads < 64 || tn.lines_threads > 1024 || tn.lines_threads % 64) return FPSSFT_ERR_INVALID_ARG;
@@ -689,6 +689,18 @@ fpssft_status fpssft_execute_batched(fpssft_plan_t p, const void* const* xs, con
   hipStream_t st = (hipStream_t)stream;
   HIP_TRY(p->xs_tab.update(xs, st));
   HIP_TRY(p->outs_tab.update(op.data(), st));
+  if (p->tune.direct_launch) {
+    // The same persistent launches straight on the stream: a graph of one
+    // kernel per instantiation saves nothing here and its launch leaves the
+    // GPU idle for several microseconds between steps.
+    for (size_t gi = 0; gi < p->groups.size(); ++gi) {
+      const Group& g = p->groups[gi];
+      HIP_TRY(fpssft::launch_solve_batched(p->ctx, g.key, (const float2* const*)p->xs_tab.dev,
+                                           (const OutPtrs*)p->outs_tab.dev, p->d_order + g.first, g.count,
+                                           p->d_queue + 2 * gi, g.grid, g.lds_solve, p->tune.block_threads, st));
+    }
+    return FPSSFT_OK;
+  }
   if (!p->gexec) {
     // One graph: one persistent launch per group (each launch finds its
     // queue counters at zero and leaves them so).

@@ -5,6 +5,8 @@ with HIP events around repeated launches:
 
   solve    block_threads x max_radix  -> persistent batched solve (one
            graph replay over all cubes)
+  launch   direct_launch              -> the same solve replayed from its HIP
+           graph or launched directly on the stream
   lines    lines_wg x lines_threads   -> line gather + FFT over every cube's
            whole iteration budget
   plain    chunk_iters                -> plain per-cube path over a subset
@@ -73,7 +75,7 @@ def tune(specs, xs, reps: int = 10, plain_cubes: int = 128, log=print) -> dict:
     from . import Plan
 
     best = {}
-    results = {"solve": [], "lines": [], "plain": []}
+    results = {"solve": [], "launch": [], "lines": [], "plain": []}
 
     # 1. persistent batched solve
     ref = None
@@ -91,6 +93,21 @@ def tune(specs, xs, reps: int = 10, plain_cubes: int = 128, log=print) -> dict:
         if ok and (best_ms is None or ms < best_ms):
             best_ms, best["solve"] = ms, tn
         del plan, bound
+
+    # 1b. graph replay or direct launches of the persistent solve
+    best_ms = None
+    for dl in (0, 1):
+        tn = dict(best["solve"], direct_launch=dl)
+        plan = Plan(specs, tuning=tn)
+        bound = plan.bind(xs)
+        ms = _time_ms(torch, bound.run_batched, reps)
+        ok = _same(ref, _decisions(bound.outs))
+        results["launch"].append(dict(direct_launch=dl, ms=round(ms, 4), same_decisions=ok))
+        log(f"solve direct_launch={dl}: {ms * 1e3:.1f} us{'' if ok else '  (decisions differ: rejected)'}")
+        if ok and (best_ms is None or ms < best_ms):
+            best_ms, best["launch"] = ms, dict(direct_launch=dl)
+        del plan, bound
+    best["solve"] = dict(best["solve"], **best["launch"])
 
     # 2. line gather + FFT
     best_ms = None
@@ -147,7 +164,7 @@ def load(arch: str, workload: str, path: str = DEFAULT_PATH):
         return None
     if not ent:
         return None
-    keys = ("block_threads", "max_radix", "chunk_iters", "lines_wg", "lines_threads")
+    keys = ("block_threads", "max_radix", "chunk_iters", "lines_wg", "lines_threads", "direct_launch")
     return {k: ent[k] for k in keys if k in ent}
 
 

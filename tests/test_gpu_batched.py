@@ -99,7 +99,8 @@ def test_cfg4_full_batch_parity(F):
             assert {tuple(f) for f in ref.freqs.tolist()} == {tuple(f) for f in cubes[c].freqs.tolist()}
 
 
-@pytest.mark.parametrize("tuning", [dict(block_threads=128), dict(block_threads=512, max_radix=4)])
+@pytest.mark.parametrize("tuning", [dict(block_threads=128), dict(block_threads=512, max_radix=4),
+                                    dict(direct_launch=1), dict(direct_launch=0)])
 def test_batched_launch_shapes_agree(F, tuning):
     cubes = W.cfg4(B=40, seed=9)
     plan, specs, xs = batched_setup(F, cubes, tuning=tuning)

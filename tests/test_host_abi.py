@@ -123,7 +123,8 @@ def test_tuning_cache_roundtrip(tmp_path):
     from paper_1711_11407_amd import tune
     path = str(tmp_path / "t.json")
     assert tune.load("gfx950", "batched", path) is None
-    out = dict(tuning=dict(block_threads=128, max_radix=4, chunk_iters=2, lines_wg=4, lines_threads=256),
+    out = dict(tuning=dict(block_threads=128, max_radix=4, chunk_iters=2, lines_wg=4, lines_threads=256,
+                           direct_launch=1),
                results={"solve": []})
     tune.save("gfx950", "batched", out, path)
     tune.save("gfx942", "batched", dict(out, tuning=dict(block_threads=64)), path)
