@@ -230,6 +230,11 @@ __device__ __forceinline__ SolveLds carve_solve_lds(char* smem, int L, int rec_l
 // Wave path of the solve loop (L = 64 E, 64 <= L <= 512, one wave per
 // line): wave w holds line w's values at l = lane + 64 e in registers.
 constexpr int kEMax = 8;
+#ifndef FPS_DECODE_BINS
+#define FPS_DECODE_BINS 2
+#endif
+// Bins per thread in one decode pass (one exchange barrier per pass).
+constexpr int kDecodeBins = FPS_DECODE_BINS;
 
 template <int D, bool kPow2>
 __device__ __forceinline__ void wave_prefetch(float2 (&pf)[kEMax], int E, const Geo<D>& g,
@@ -526,82 +531,112 @@ __device__ __forceinline__ void solve_cube(const CubeDesc& cd, const float2* __r
       lds_barrier();
     }
 
-    // Test, decode and append, bins in ascending order.
+    // Test, decode and append, bins in ascending order: a pass covers up to
+    // kDecodeBins bins per thread (bin m0 + j B + tid for the j-th), with one
+    // exchange barrier for all of them.
     bool nonzero = false;
     bool full = false;
     bool any = false;
-    for (uint32_t m0 = 0; m0 < L; m0 += B) {
-      const uint32_t m = m0 + tid;
-      bool cand = false;
-      int f[D];
-      float2 amp = make_float2(0.f, 0.f);
-      if (m < L) {
-        float2 r[D + 1];
+    constexpr int kNB = D >= 4 ? 1 : kDecodeBins;  // 4-D: register budget
+    const int nbp = min(kNB, (int)((L + (uint32_t)B - 1) / (uint32_t)B));
+    for (uint32_t m0 = 0; m0 < L; m0 += (uint32_t)(B * nbp)) {
+      bool cand[kNB];
+      int f[kNB][D];
+      float2 amp[kNB];
+      int slot[kNB], before[kNB], wcnt[kNB];
+      int wall = 0;
 #pragma unroll
-        for (int i = 0; i <= D; ++i) r[i] = S[i * L + m];
-        if (conc) {
+      for (int j = 0; j < kNB; ++j) {
+        const uint32_t m = m0 + (uint32_t)(j * B) + tid;
+        cand[j] = false;
+        amp[j] = make_float2(0.f, 0.f);
+        slot[j] = -1;
+        if (j < nbp && m < L) {
+          float2 r[D + 1];
 #pragma unroll
-          for (int i = 0; i <= D; ++i) {
-            r[i] = c_sub(r[i], s.P[i * L + m]);
-            s.P[i * L + m] = make_float2(0.f, 0.f);
+          for (int i = 0; i <= D; ++i) r[i] = S[i * L + m];
+          if (conc) {
+#pragma unroll
+            for (int i = 0; i <= D; ++i) {
+              r[i] = c_sub(r[i], s.P[i * L + m]);
+              s.P[i * L + m] = make_float2(0.f, 0.f);
+            }
           }
+          cand[j] = decode_bin<D, kPow2>(g, al, ta, r, m, th0, rho, gtol, tw, avg, nonzero, f[j], amp[j]);
         }
-        cand = decode_bin<D, kPow2>(g, al, ta, r, m, th0, rho, gtol, tw, avg, nonzero, f, amp);
+        const unsigned long long bal = __ballot(cand[j] ? 1 : 0);
+        wcnt[j] = __popcll(bal);
+        before[j] = __popcll(bal & ((1ull << lane) - 1ull));
+        wall += wcnt[j];
       }
-      int slot = -1;
-      const unsigned long long bal = __ballot(cand ? 1 : 0);
-      const int wcnt = __popcll(bal);
-      const int before = __popcll(bal & ((1ull << lane) - 1ull));
-      if (kRecLds && wcnt > 0) {
+      if (kRecLds && wall > 0) {
         // Append to the LDS list now (one atomic per wave), so that the next
         // iteration's peel needs no barrier after the exchange below.
-        const int first = __builtin_ctzll(bal);
         int base = 0;
-        if (lane == first) base = atomicAdd(s.cnt, wcnt);
-        base = __builtin_amdgcn_readlane(base, first);
-        slot = base + before;
-        if (cand && slot < cd.rec_lds) {
+        if (lane == 0) base = atomicAdd(s.cnt, wall);
+        base = __builtin_amdgcn_readlane(base, 0);
 #pragma unroll
-          for (int k = 0; k < D; ++k) s.rec_f[slot * D + k] = f[k];
-          s.rec_a[slot] = amp;
-          s.rec_t[slot] = t;
-          s.rec_m[slot] = (int32_t)m;
+        for (int j = 0; j < kNB; ++j) {
+          slot[j] = base + before[j];
+          base += wcnt[j];
+          if (cand[j] && slot[j] < cd.rec_lds) {
+#pragma unroll
+            for (int k = 0; k < D; ++k) s.rec_f[slot[j] * D + k] = f[j][k];
+            s.rec_a[slot[j]] = amp[j];
+            s.rec_t[slot[j]] = t;
+            s.rec_m[slot[j]] = (int32_t)(m0 + (uint32_t)(j * B) + tid);
+          }
         }
       }
+      // exchange word: 8 bits of candidate count per bin set, nonzero flag
       const bool wnz = __ballot(nonzero ? 1 : 0) != 0ull;
-      if (lane == 0) s.wsum[xpar * 16 + wv] = wcnt | (wnz ? 0x10000 : 0);
+      int wword = wnz ? (1 << 24) : 0;
+#pragma unroll
+      for (int j = 0; j < kNB; ++j) wword |= wcnt[j] << (8 * j);
+      if (lane == 0) s.wsum[xpar * 16 + wv] = wword;
       lds_barrier();
       // one LDS read per lane, then the words are taken from the lanes
       const int word = lane < nw ? s.wsum[xpar * 16 + lane] : 0;
-      int pos = before, tot = 0;
+      int pre[kNB], tot[kNB];
+#pragma unroll
+      for (int j = 0; j < kNB; ++j) pre[j] = tot[j] = 0;
       any = false;
       for (int w = 0; w < nw; ++w) {
         const int v = __builtin_amdgcn_readlane(word, w);
-        pos += (w < wv) ? (v & 0xffff) : 0;
-        tot += v & 0xffff;
-        any |= (v >> 16) != 0;
+#pragma unroll
+        for (int j = 0; j < kNB; ++j) {
+          const int c = (v >> (8 * j)) & 0xff;
+          pre[j] += (w < wv) ? c : 0;
+          tot[j] += c;
+        }
+        any |= (v >> 24) != 0;
       }
       xpar ^= 1;
-      if (cand) {
-        const int idx = kc + pos;
-        if (kRecLds && slot < cd.rec_lds) {
-          // written out at the end of the cube (global stores issued now
-          // would queue behind the next iteration's gathers)
-          s.rec_p[slot] = idx;
-        } else if (idx < max_k) {
+      int done = 0;  // candidates of the earlier bin sets of this pass
 #pragma unroll
-          for (int k = 0; k < D; ++k) st_gi(out.freqs, idx * D + k, f[k]);
-          st_g(oamps, idx, amp);
-          st_gi(out.rec_iter, idx, t);
-          st_gi(out.rec_bin, idx, (int32_t)m);
+      for (int j = 0; j < kNB; ++j) {
+        if (cand[j]) {
+          const int idx = kc + done + pre[j] + before[j];
+          if (kRecLds && slot[j] < cd.rec_lds) {
+            // written out at the end of the cube (global stores issued now
+            // would queue behind the next iteration's gathers)
+            s.rec_p[slot[j]] = idx;
+          } else if (idx < max_k) {
+#pragma unroll
+            for (int k = 0; k < D; ++k) st_gi(out.freqs, idx * D + k, f[j][k]);
+            st_g(oamps, idx, amp[j]);
+            st_gi(out.rec_iter, idx, t);
+            st_gi(out.rec_bin, idx, (int32_t)(m0 + (uint32_t)(j * B) + tid));
+          }
         }
+        done += tot[j];
       }
-      if (kc + tot > max_k) {
+      if (kc + done > max_k) {
         full = true;
         kc = max_k;
         break;
       }
-      kc += tot;
+      kc += done;
     }
     // Records kept in global memory are read by other threads next
     // iteration: make the stores visible across the work-group.
