@@ -197,12 +197,73 @@ def summarize_counters(dirs):
     print(json.dumps(out, indent=1))
 
 
+def lines_3d(torch, F, dev, args):
+    """The second line-FFT aggregate: 32 independent 128^3 cubes, each over its
+    whole budget T_max = 4096 iterations of 4 lines of 128 samples (16 MiB
+    gathered per cube, 512 MiB in all). The inputs are seeded Gaussian cubes
+    drawn on the device: the line FFT's time does not depend on the values."""
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(3)
+    n = 32
+    xs = [torch.randn((128, 128, 128), dtype=torch.complex64, device=dev, generator=gen) for _ in range(n)]
+    specs = [F.CubeSpec((128, 128, 128), seed=100 + i, max_k=64) for i in range(n)]
+    plan = F.Plan(specs, tuning=load_tuning("batched"))
+    bound = plan.bind(xs)
+    for _ in range(max(1, args.warmup)):
+        bound.run_lines_all()
+    torch.cuda.synchronize()
+    ms = event_time_ms(torch, bound.run_lines_all, max(1, args.steps))
+    samples = sum(plan.info[c][1] * 4 * plan.info[c][0] for c in range(n))
+    alg = 2 * 8 * samples
+    gbs = alg / (ms * 1e-3) / 1e9
+    log(f"line FFT 3-D: {ms:.3f} ms, {gbs:.0f} GB/s ({100 * gbs / HBM_PEAK_GBS:.1f}% of 8 TB/s)")
+    return {"kernel": "k_lines", "workload": "32 x 128^3 cubes, T_max = 4096 each (4 lines of 128 per iteration)",
+            "samples": int(samples), "ms_per_launch": round(ms, 4), "bound": "hbm", "achieved": round(gbs, 1),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4), "algorithmic_bytes": int(alg)}
+
+
+def per_config(torch, F, W, dev, args, with_oracle=True):
+    """The single-cube workloads on the plain path (one fpssft_execute each,
+    events around repeated calls) beside the FP64 oracle on one host core
+    (one run, cube generation excluded)."""
+    out = {}
+    cases = [("cfg1", W.cfg1(), W.NOISELESS_THRESH, 64),
+             ("cfg2", W.cfg2(), None, 8192),
+             ("cfg3", W.cfg3(), W.NOISELESS_THRESH, 1024)]
+    for name, cube, th, max_k in cases:
+        if th is None:
+            th = W.cfg2_thresh(cube, 256)
+        spec = F.CubeSpec(cube.dims, seed=cube.schedule_seed, max_k=max_k, **th)
+        plan = F.Plan([spec], tuning=load_tuning("batched"))
+        x = torch.from_numpy(cube.x).to(dev)
+        res = plan.execute(0, x)
+        torch.cuda.synchronize()
+        ms = event_time_ms(torch, lambda: plan.execute(0, x, res), max(3, args.steps))
+        h = res.host()
+        ent = {"dims": list(cube.dims), "K": int(len(cube.amps)), "gpu_ms": round(ms, 4),
+               "gpu_transforms_per_s": round(1e3 / ms, 1), "iterations": int(h["iters"]), "records": int(h["k"])}
+        if with_oracle:
+            import oracle as O
+            T = plan.max_iters(0)
+            al, ta = O.schedule(cube.dims, T, cube.schedule_seed)
+            t0 = time.perf_counter()
+            O.run(cube.x, al, ta, O.Params(zero_thresh=spec.zero_thresh, mag_rel_tol=spec.mag_rel_tol,
+                                            grid_tol=spec.grid_tol, max_iters=T, max_k=max_k))
+            om = (time.perf_counter() - t0) * 1e3
+            ent.update({"oracle_ms": round(om, 2), "oracle_transforms_per_s": round(1e3 / om, 2),
+                        "gpu_over_oracle": round(om / ms, 1)})
+        log(f"{name}: GPU {ms:.4f} ms ({h['iters']} iterations, {h['k']} records)"
+            + (f", oracle {ent['oracle_ms']} ms" if with_oracle else ""))
+        out[name] = ent
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--only", choices=["copy", "lines", "batched", "plain"], default=None)
+    ap.add_argument("--only", choices=["copy", "lines", "lines3d", "batched", "plain", "configs"], default=None)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--traffic-from", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
                     help="write profiles/traffic.json from rocprofv3 --pmc output directories")
@@ -266,7 +327,22 @@ def main():
             "frac": round(gbs / HBM_PEAK_GBS, 4), "algorithmic_bytes": int(alg),
             "traffic": tr}
         log(f"line FFT: {ms:.3f} ms, {gbs:.0f} GB/s ({100 * gbs / HBM_PEAK_GBS:.1f}% of 8 TB/s)")
+        # Cold caches: a 512 MiB scratch write before each launch evicts L2
+        # and the Infinity Cache; each launch timed on its own.
+        scratch = torch.empty(1 << 26, dtype=torch.float64, device=dev)
+        cold = []
+        for _ in range(max(3, args.steps // 4)):
+            scratch.fill_(1.0)
+            cold.append(event_time_ms(torch, bound.run_lines_all, 1))
+        cms = float(np.median(cold))
+        result["line_fft"]["cold_ms_per_launch"] = round(cms, 4)
+        result["line_fft"]["cold_achieved"] = round(alg / (cms * 1e-3) / 1e9, 1)
+        del scratch
+        log(f"line FFT, caches flushed: {cms:.3f} ms")
         bound.spectra = None
+
+    if args.only in (None, "lines3d"):
+        result["line_fft_3d"] = lines_3d(torch, F, dev, args)
 
     if args.only in (None, "batched"):
         for _ in range(args.warmup):
@@ -312,6 +388,9 @@ def main():
             result["plain"]["batched_over_plain"] = round(result["value"] / pv, 2)
         log(f"plain: {ms:.3f} ms for {B} cubes, {pv:.0f} transforms/s")
 
+    if args.only in (None, "configs"):
+        result["configs"] = per_config(torch, F, W, dev, args, with_oracle=not args.no_cpu)
+
     if args.only is not None:
         log(json.dumps(result))
         return
@@ -324,7 +403,7 @@ def main():
         "config": {"workload": WORKLOAD, "global_batch": B, "parallelism": "single GPU",
                    "tuning": tuning or "library defaults"},
         "roofline": result["roofline"], "line_fft": result["line_fft"], "plain": result["plain"],
-        "accuracy": result["accuracy"],
+        "accuracy": result["accuracy"], "line_fft_3d": result["line_fft_3d"], "configs": result["configs"],
     }
     if not args.no_cpu:
         log("CPU baseline (oracle)")
