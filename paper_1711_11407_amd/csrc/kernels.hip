@@ -230,11 +230,8 @@ __device__ __forceinline__ SolveLds carve_solve_lds(char* smem, int L, int rec_l
 // Wave path of the solve loop (L = 64 E, 64 <= L <= 512, one wave per
 // line): wave w holds line w's values at l = lane + 64 e in registers.
 constexpr int kEMax = 8;
-#ifndef FPS_DECODE_BINS
-#define FPS_DECODE_BINS 2
-#endif
 // Bins per thread in one decode pass (one exchange barrier per pass).
-constexpr int kDecodeBins = FPS_DECODE_BINS;
+constexpr int kDecodeBins = 2;
 
 template <int D, bool kPow2>
 __device__ __forceinline__ void wave_prefetch(float2 (&pf)[kEMax], int E, const Geo<D>& g,

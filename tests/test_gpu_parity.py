@@ -53,6 +53,9 @@ SHAPES = [
     ((128, 128), 300, 0),
     ((256, 256), 1280, 0),     # the paper's K = 5 N0 regime
     ((7, 9), 4, 40),           # L = 63 = 7 * 9
+    ((384, 96), 200, 0),       # L = 384: a two-bin decode pass with a ragged second bin set
+    ((640, 128), 250, 0),      # L = 640: two decode passes, the second ragged
+    ((96, 96, 96), 300, 40),   # D = 3, L = 96 on the block path
 ]
 
 
