@@ -403,43 +403,6 @@ __device__ __forceinline__ float2* block_fft(float2* a, float2* b, int nl, int L
 }
 
 // ---------------------------------------------------------------------------
-// Exclusive prefix count of `flag` over the block in thread order (wave64
-// ballots, per-wave counts in LDS `wsum`). Two barriers.
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ int block_prefix(bool flag, int* wsum, int* total) {
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  const int nw = (blockDim.x + 63) >> 6;
-  const unsigned long long bal = __ballot(flag ? 1 : 0);
-  const int before = __popcll(bal & ((1ull << lane) - 1ull));
-  if (lane == 0) wsum[wave] = __popcll(bal);
-  lds_barrier();
-  int base = 0, tot = 0;
-  for (int w = 0; w < nw; ++w) {
-    const int c = wsum[w];
-    base += (w < wave) ? c : 0;
-    tot += c;
-  }
-  lds_barrier();
-  *total = tot;
-  return base + before;
-}
-
-// True on every thread iff `flag` is true on some thread. Two barriers.
-__device__ __forceinline__ bool block_any(bool flag, int* wsum) {
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  const int nw = (blockDim.x + 63) >> 6;
-  const unsigned long long bal = __ballot(flag ? 1 : 0);
-  if (lane == 0) wsum[wave] = bal != 0ull;
-  lds_barrier();
-  int any = 0;
-  for (int w = 0; w < nw; ++w) any |= wsum[w];
-  lds_barrier();
-  return any != 0;
-}
-
-// ---------------------------------------------------------------------------
 // The D+1 samples of line position l (Eq. sample_slice): line 0 at `flat`,
 // line i at flat + step[i-1]. Line D is the shift along the contiguous last
 // dimension, so unless that coordinate wraps its sample is the next element:
