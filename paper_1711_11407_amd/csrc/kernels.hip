@@ -333,14 +333,21 @@ __device__ __forceinline__ bool decode_bin(const Geo<D>& g, const uint32_t (&al)
     const float mi = sqrtf(ri.x * ri.x + ri.y * ri.y);
     nonzero |= mi > th0;
     cand = cand && (fabsf(mi - mag0) <= rho * mag0);
-    const float2 z = c_mulc(ri, r0);
-    const float phi = atan2f(z.y, z.x);
-    const float u = ((float)g.dims[k] * phi) * kInv2Pi;
-    const float v = rintf(u);
-    if (gtol >= 0.f) cand = cand && (fabsf(u - v) <= gtol);
-    int fi = (int)v % (int)g.dims[k];
-    if (fi < 0) fi += (int)g.dims[k];
-    f[k] = fi;
+  }
+  // The phase decode only for bins that pass the magnitude tests (the same
+  // decisions: every test must hold); waves without such a bin skip it.
+  if (cand) {
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      const float2 z = c_mulc(r[k + 1], r0);
+      const float phi = atan2f(z.y, z.x);
+      const float u = ((float)g.dims[k] * phi) * kInv2Pi;
+      const float v = rintf(u);
+      if (gtol >= 0.f) cand = cand && (fabsf(u - v) <= gtol);
+      int fi = (int)v % (int)g.dims[k];
+      if (fi < 0) fi += (int)g.dims[k];
+      f[k] = fi;
+    }
   }
   if (cand) {
     uint32_t b = 0, q = 0;
