@@ -208,6 +208,14 @@ int64_t fpssft_plan_spectra_elems(fpssft_plan_t plan);
 
 /* ---- the hot path ------------------------------------------------------ */
 
+/* Errors of the calls below, returned before anything is enqueued:
+ * INVALID_ARG for a NULL plan, input, output or gradient pointer (every
+ * pointer field of an fpssft_out included), a cube index outside
+ * [0, batch), or an iteration range outside [0, T_max); UNSUPPORTED as
+ * stated per call. HIP errors while enqueueing return FPSSFT_ERR_HIP.
+ * Algorithmic outcomes (OK, INCOMPLETE, CAPACITY) are not errors: they go
+ * to info[2] on the device. The calls do not synchronize the stream. */
+
 /* Plain per-cube FPS-SFT on cube `cube` of the plan: the line gather + FFT
  * kernel transforms the first chunk of iterations in parallel, then one
  * work-group peels, tests, decodes and appends iteration by iteration,
