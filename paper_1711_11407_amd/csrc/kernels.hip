@@ -176,7 +176,7 @@ __global__ void k_lines(const CubeDesc* __restrict__ descs, const LineItem* __re
 // One cube, one work-group.
 // ---------------------------------------------------------------------------
 struct SolveLds {
-  float2* bufA;    // lines; on the wave path each line's row is padded
+  float2* bufA;    // [(D+1) L] the line spectra, row i = line i
   float2* bufB;    // the block FFT's second buffer (block path)
   float2* P;       // [(D+1) L] peel accumulator (wave path; block path with
                    // the time-domain construction-subtraction)

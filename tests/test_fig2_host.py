@@ -43,3 +43,19 @@ def test_perfect_criterion_on_oracle_results():
         assert not fig2.perfect(bad, c)
         short = dict(host, k=r.k - 1, freqs=r.freqs[:-1], amps=r.amps[:-1])
         assert not fig2.perfect(short, c)
+
+
+def test_image_like_support_is_clustered_and_exact():
+    c = W.image_like((64, 72), 300, seed=5)
+    f = {tuple(v) for v in c.freqs.tolist()}
+    assert len(f) == 300 and len(c.amps) == 300
+    assert np.all(np.isreal(c.amps)) and c.amps.real.min() >= 0.5 and c.amps.real.max() <= 1.5
+    # clustered: most pixels have a 4-neighbour in the support (uniform: ~26%)
+    nb = sum(any(((a + da) % 64, (b + db) % 72) in f for da, db in ((1, 0), (-1, 0), (0, 1), (0, -1)))
+             for a, b in f)
+    assert nb / len(f) > 0.8
+    # duality: the DFT of x is the image
+    X = np.fft.fftn(c.x.astype(np.complex128)) / c.x.size
+    img = np.zeros((64, 72), dtype=np.complex128)
+    img[tuple(c.freqs.T)] = c.amps
+    assert np.abs(X - img).max() < 1e-5

@@ -273,3 +273,23 @@ def test_image_scale_sparsity(F):
     log(f"K=8411 on 512x576: status {got['status']} after {got['iters']} iterations "
         f"({100.0 * got['iters'] * 3 * 4608 / (512 * 576):.1f}% of the samples)")
     assert got["status"] == O.STATUS_OK
+
+
+def test_clustered_image_512x576(F):
+    """A pixel-sparse clustered image (rectangular blobs, 2.85% of the
+    pixels, real intensities) through duality, at the image experiment's
+    shape: plain and batched equal the oracle record by record."""
+    torch, dev = torch_dev()
+    cube = W.image_like((512, 576), 8411, seed=2017)
+    spec = spec_for(F, cube.dims, cube.schedule_seed, max_k=16384)
+    plan = F.Plan([spec])
+    x = torch.from_numpy(cube.x).to(dev)
+    got = plan.execute(0, x).host()
+    bat = plan.execute_batched([x])[0].host()
+    ref, _, _ = oracle_for(plan, 0, cube.x, spec)
+    compare(got, ref, "clustered image, plain")
+    compare(bat, ref, "clustered image, batched")
+    assert got["status"] == O.STATUS_OK
+    assert {tuple(f) for f in got["freqs"].tolist()} == {tuple(f) for f in cube.freqs.tolist()}
+    log(f"clustered image: {got['iters']} iterations ({100.0 * got['iters'] * 3 * 4608 / (512 * 576):.1f}% "
+        f"of the samples)")

@@ -110,6 +110,35 @@ def plant(dims: Sequence[int], K: int, seed: int, mag="unit",
                 noise_sigma=sigma)
 
 
+def image_like(dims: Sequence[int], K: int, seed: int) -> Cube:
+    """A pixel-sparse 2-D "image" with clustered support, used through
+    duality: the image is the sparse spectrum, x = N IDFT(image). Blobs are
+    axis-aligned rectangles of 1..12 x 1..12 pixels at uniform positions
+    (wrapping), added until the support holds exactly K pixels (the last
+    blob is trimmed). Intensities are real, U[0.5, 1.5], as in a magnitude
+    image. Stands in for the image experiment of Sec. 3, whose image is not
+    available."""
+    if len(dims) != 2:
+        raise ValueError("image_like is 2-D")
+    rng = np.random.default_rng(seed)
+    n0, n1 = (int(d) for d in dims)
+    mask = np.zeros((n0, n1), dtype=bool)
+    order = []
+    while len(order) < K:
+        h, w = (int(v) for v in rng.integers(1, 13, size=2))
+        r0, c0 = int(rng.integers(0, n0)), int(rng.integers(0, n1))
+        for i in range(h):
+            for j in range(w):
+                p = ((r0 + i) % n0, (c0 + j) % n1)
+                if not mask[p] and len(order) < K:
+                    mask[p] = True
+                    order.append(p)
+    freqs = np.array(sorted(order), dtype=np.int64)
+    amps = rng.uniform(0.5, 1.5, size=K).astype(np.complex128)
+    x = synthesize(dims, freqs, amps)
+    return Cube(x=x.astype(np.complex64), freqs=freqs, amps=amps, seed=int(seed))
+
+
 def random_dense(dims: Sequence[int], seed: int) -> np.ndarray:
     """A dense random complex cube (not sparse), for identity checks."""
     rng = np.random.default_rng(seed)
