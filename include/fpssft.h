@@ -132,12 +132,16 @@ typedef struct {
  *  chunk_iters    iterations the plain path gathers and transforms ahead
  *                 in parallel before its sequential decode (>= 0)
  *  lines_wg       consecutive iterations per work item of the persistent
- *                 line gather + FFT kernel (>= 1)
+ *                 line gather + FFT kernel (>= 1) when lines_samples < 0
  *  lines_threads  threads per work-group of that kernel (64..1024)
  *  direct_launch  fpssft_execute_batched: 0 replays one HIP graph holding
  *                 the persistent solve launches (default), 1 launches them
  *                 on the stream directly (no graph; the launches may then be
- *                 captured into the caller's own graph) */
+ *                 captured into the caller's own graph)
+ *  lines_samples  > 0: a work item of the line kernel takes
+ *                 max(1, lines_samples / ((D+1) L)) consecutive iterations
+ *                 of its cube (about that many samples, whatever the line
+ *                 length); < 0: lines_wg iterations; 0: default 3072 */
 typedef struct {
   int32_t block_threads;
   int32_t max_radix;
@@ -145,6 +149,7 @@ typedef struct {
   int32_t lines_wg;
   int32_t lines_threads;
   int32_t direct_launch;
+  int32_t lines_samples;
 } fpssft_tuning;
 
 typedef struct fpssft_plan_st* fpssft_plan_t;

@@ -149,6 +149,8 @@ class Plan:
             tn.lines_wg = int(tuning.get("lines_wg", 0))
             tn.lines_threads = int(tuning.get("lines_threads", 0))
             tn.direct_launch = int(tuning.get("direct_launch", 0))
+            # an explicit lines_wg without lines_samples means lines_wg
+            tn.lines_samples = int(tuning.get("lines_samples", -1 if "lines_wg" in tuning else 0))
         h = C.c_void_p()
         B.check(B.lib().fpssft_plan_create(descs, len(self.specs), C.byref(tn) if tn else None, C.byref(h)),
                 "plan_create")

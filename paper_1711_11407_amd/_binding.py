@@ -51,6 +51,7 @@ class Tuning(C.Structure):
         ("lines_wg", C.c_int32),
         ("lines_threads", C.c_int32),
         ("direct_launch", C.c_int32),
+        ("lines_samples", C.c_int32),
     ]
 
 

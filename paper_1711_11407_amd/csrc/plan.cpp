@@ -347,7 +347,7 @@ fpssft_status build_plan(const fpssft_desc* descs, int32_t batch, const fpssft_t
   if (v <= 2048) return FPSSFT_ERR_UNSUPPORTED;
   p->lds_max = (size_t)v - 1024;
   p->B = batch;
-  fpssft_tuning tn{256, 8, 8, 4, 256, 0};
+  fpssft_tuning tn{256, 8, 8, 4, 256, 0, 3072};
   if (tuning) {
     if (tuning->block_threads) tn.block_threads = tuning->block_threads;
     if (tuning->max_radix) tn.max_radix = tuning->max_radix;
@@ -355,6 +355,7 @@ fpssft_status build_plan(const fpssft_desc* descs, int32_t batch, const fpssft_t
     if (tuning->lines_wg) tn.lines_wg = tuning->lines_wg;
     if (tuning->lines_threads) tn.lines_threads = tuning->lines_threads;
     tn.direct_launch = tuning->direct_launch != 0;
+    if (tuning->lines_samples) tn.lines_samples = tuning->lines_samples;
   }
   if (tn.block_threads < 64 || tn.block_threads > 512 || tn.block_threads % 64) return FPSSFT_ERR_INVALID_ARG;
   if (tn.lines_threads < 64 || tn.lines_threads > 1024 || tn.lines_threads % 64) return FPSSFT_ERR_INVALID_ARG;
@@ -478,11 +479,14 @@ fpssft_status build_plan(const fpssft_desc* descs, int32_t batch, const fpssft_t
         g.maxL_serial = std::max(g.maxL_serial, cd.L);
       else
         g.maxL = std::max(g.maxL, cd.L);
-      for (int32_t t = 0; t < cd.T; t += tn.lines_wg) {
+      // iterations per item: about lines_samples samples, else lines_wg
+      const int32_t wg = tn.lines_samples > 0 ? std::max<int32_t>(1, tn.lines_samples / ((cd.D + 1) * cd.L))
+                                              : tn.lines_wg;
+      for (int32_t t = 0; t < cd.T; t += wg) {
         LineItem li{};
         li.cube = c;
         li.t0 = t;
-        li.count = std::min(tn.lines_wg, cd.T - t);
+        li.count = std::min(wg, cd.T - t);
         li.out_off = cd.spec_off + (int64_t)t * (cd.D + 1) * cd.L;
         p->items.push_back(li);
       }

@@ -7,7 +7,7 @@ with HIP events around repeated launches:
            graph replay over all cubes)
   launch   direct_launch              -> the same solve replayed from its HIP
            graph or launched directly on the stream
-  lines    lines_wg x lines_threads   -> line gather + FFT over every cube's
+  lines    lines_samples x lines_threads -> line gather + FFT over every cube's
            whole iteration budget
   plain    chunk_iters                -> plain per-cube path over a subset
 
@@ -30,7 +30,7 @@ import time
 DEFAULT_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning.json")
 
 SOLVE_GRID = dict(block_threads=(64, 128, 192, 256, 320, 384, 448, 512), max_radix=(4, 8))
-LINES_GRID = dict(lines_wg=(1, 2, 4, 8), lines_threads=(64, 128, 256, 512))
+LINES_GRID = dict(lines_samples=(1536, 3072, 6144), lines_threads=(64, 128, 256, 512))
 PLAIN_GRID = dict(chunk_iters=(0, 2, 4, 8, 16))
 
 
@@ -111,15 +111,15 @@ def tune(specs, xs, reps: int = 10, plain_cubes: int = 128, log=print) -> dict:
 
     # 2. line gather + FFT
     best_ms = None
-    for wg, lt in itertools.product(LINES_GRID["lines_wg"], LINES_GRID["lines_threads"]):
-        tn = dict(best["solve"], lines_wg=wg, lines_threads=lt)
+    for ns, lt in itertools.product(LINES_GRID["lines_samples"], LINES_GRID["lines_threads"]):
+        tn = dict(best["solve"], lines_samples=ns, lines_threads=lt)
         plan = Plan(specs, tuning=tn)
         bound = plan.bind(xs)
         ms = _time_ms(torch, bound.run_lines_all, reps)
-        results["lines"].append(dict(lines_wg=wg, lines_threads=lt, ms=round(ms, 4)))
-        log(f"lines lines_wg={wg} lines_threads={lt}: {ms * 1e3:.1f} us")
+        results["lines"].append(dict(lines_samples=ns, lines_threads=lt, ms=round(ms, 4)))
+        log(f"lines lines_samples={ns} lines_threads={lt}: {ms * 1e3:.1f} us")
         if best_ms is None or ms < best_ms:
-            best_ms, best["lines"] = ms, dict(lines_wg=wg, lines_threads=lt)
+            best_ms, best["lines"] = ms, dict(lines_samples=ns, lines_threads=lt)
         del plan, bound
 
     # 3. plain per-cube path on a subset
@@ -164,7 +164,8 @@ def load(arch: str, workload: str, path: str = DEFAULT_PATH):
         return None
     if not ent:
         return None
-    keys = ("block_threads", "max_radix", "chunk_iters", "lines_wg", "lines_threads", "direct_launch")
+    keys = ("block_threads", "max_radix", "chunk_iters", "lines_wg", "lines_threads", "direct_launch",
+            "lines_samples")
     return {k: ent[k] for k in keys if k in ent}
 
 

@@ -188,15 +188,17 @@ def test_noisy_cfg2_reports_agreement(F):
         f"{len(g & o)/max(1, len(g | o)):.2f}")
 
 
-def test_lines_fft_all_mixed_lengths_matches_single(F):
+@pytest.mark.parametrize("tuning", [None, dict(lines_samples=512), dict(lines_samples=20000),
+                                    dict(lines_wg=3)])
+def test_lines_fft_all_mixed_lengths_matches_single(F, tuning):
     """The persistent whole-budget line FFT over a group of cubes of mixed
-    line lengths (and a 3-D group): every packed block equals the
-    single-cube line FFT of the same iterations."""
+    line lengths (and a 3-D group), for several work-item sizes: every
+    packed block equals the single-cube line FFT of the same iterations."""
     torch, dev = torch_dev()
     shapes = [(64, 64), (128, 64), (512, 512), (64, 512), (256, 256), (128, 128, 128), (64, 128, 64)]
     T = [21, 21, 40, 21, 85, 30, 12]
     specs = [spec_for(F, d, 50 + i, max_iters=T[i]) for i, d in enumerate(shapes)]
-    plan = F.Plan(specs)
+    plan = F.Plan(specs, tuning=tuning)
     xs = [torch.from_numpy(W.random_dense(d, 60 + i).astype(np.complex64)).to(dev) for i, d in enumerate(shapes)]
     allsp = plan.lines_fft_all(xs).cpu().numpy()
     for c, d in enumerate(shapes):
