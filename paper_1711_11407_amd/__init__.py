@@ -222,7 +222,8 @@ class Plan:
         return out
 
     def execute_batched(self, xs, outs: Optional[Sequence[Result]] = None, stream=None):
-        """All cubes in one persistent graph launch (fpssft_execute_batched)."""
+        """All cubes in one persistent launch per kernel instantiation, replayed
+        from a HIP graph or launched directly (fpssft_execute_batched)."""
         if len(xs) != len(self):
             raise ValueError("one input per cube")
         for c, x in enumerate(xs):
