@@ -1,5 +1,6 @@
-"""Batched persistent path (one graph launch for many uneven cubes) against
-the plain path and the FP64 oracle."""
+"""Batched persistent path (one persistent launch per kernel instantiation
+for many uneven cubes, replayed from a HIP graph or launched directly)
+against the plain path and the FP64 oracle."""
 import numpy as np
 import pytest
 
@@ -24,7 +25,10 @@ def batched_setup(F, cubes, max_k=512, tuning=None):
     return plan, specs, xs
 
 
-def test_batched_small_mixed_equals_oracle(F):
+@pytest.mark.parametrize("direct", [0, 1])
+def test_batched_small_mixed_equals_oracle(F, direct):
+    """Mixed dimensions and line lengths: several kernel instantiations in
+    one call, as one graph or as direct launches in sequence."""
     cubes = [W.plant(d, k, seed=s, mag=(0.5, 1.5)) for d, k, s in
              [((64, 64), 30, 1), ((16, 24), 10, 2), ((128, 128, 128), 200, 3), ((6, 10), 2, 4),
               ((512, 64), 120, 5), ((8, 8, 12), 15, 6), ((256, 256), 1000, 7)]]
@@ -33,9 +37,10 @@ def test_batched_small_mixed_equals_oracle(F):
         T = max(O.default_max_iters(c.dims), 30) if np.prod(c.dims) < 4096 else 0
         specs.append(spec_for(F, c.dims, c.schedule_seed, max_k=2048, max_iters=T))
     torch, dev = torch_dev()
-    plan = F.Plan(specs)
+    plan = F.Plan(specs, tuning=dict(direct_launch=direct))
     xs = [torch.from_numpy(c.x).to(dev) for c in cubes]
     outs = plan.execute_batched(xs)
+    outs = plan.execute_batched(xs, outs)   # second call: queue counters reset by the last launch
     for i, (c, o) in enumerate(zip(cubes, outs)):
         ref, _, _ = oracle_for(plan, i, c.x, specs[i])
         compare(o.host(), ref, f"cube {i} {c.dims}")

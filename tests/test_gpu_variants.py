@@ -92,7 +92,8 @@ def test_axis_schedule_recovers_separable_support(F):
     log(f"axis schedule, K=6 at 64x64: status {got['status']} after {got['iters']} iterations")
 
 
-def test_mixed_variants_in_one_batched_launch(F):
+@pytest.mark.parametrize("direct", [0, 1])
+def test_mixed_variants_in_one_batched_launch(F, direct):
     """Default, literal, averaged and axis cubes of several shapes in one
     plan: the batched launch (one persistent kernel per instantiation) gives
     every cube the oracle's result."""
@@ -105,7 +106,7 @@ def test_mixed_variants_in_one_batched_launch(F):
         T = 30 if d == (16, 24) else 0
         cubes.append(c)
         specs.append(spec_for(F, d, 960 + i, max_iters=T, max_k=256, **opt))
-    run_both(F, cubes, specs)
+    run_both(F, cubes, specs, tuning=dict(direct_launch=direct))
 
 
 def test_variant_limits(F):
