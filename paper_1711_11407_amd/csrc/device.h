@@ -7,8 +7,10 @@
 //    butterflies in registers and a generic radix for other prime factors,
 //    twiddles read from one table W_L^k = exp(-j 2 pi k / L) with exact
 //    integer exponents (Eq. hs);
-//  * block prefix count and block "any" built from wave64 ballots, and a
-//    work-group barrier that orders LDS only.
+//  * a register-only wave FFT for power-of-two lines of 64..512 points, its
+//    cross-lane butterflies on DPP row rotations, quad permutations and the
+//    gfx950 permlane swaps;
+//  * a work-group barrier that orders LDS only.
 //
 // Everything is templated on the dimension count D and on whether the line
 // length (hence every N_k, which divides it) is a power of two, so that each

@@ -5,9 +5,11 @@
 //                   many work-groups, HBM-bound.
 //  k_solve_plain    one cube in one work-group: for every iteration, the
 //                   spectra (precomputed by k_lines for the first chunk,
-//                   gathered and transformed in LDS after it), the peel of
-//                   the recovered list (construction-subtraction, Sec. 2.2,
-//                   done on the spectra), the 1-sparsity test, the phase
+//                   gathered and transformed after it: one wave per line in
+//                   registers, a block FFT in LDS, or line by line for long
+//                   lines), the peel of the recovered list
+//                   (construction-subtraction, Sec. 2.2, on the spectra, or
+//                   in time on request), the 1-sparsity test, the phase
 //                   decode and the amplitude (Eq. decoding), the ordered
 //                   append, and the stopping rule.
 //  k_solve_batched  the same per cube, persistent: work-groups take cube
@@ -16,8 +18,8 @@
 //  k_reset, k_zero  counter reset and zero fill (kernels, so that they can
 //                   sit inside a captured graph).
 //
-// Kernels are instantiated per (D, power-of-two L, records in LDS); the host
-// picks the instantiation per cube group.
+// Kernels are instantiated per (D, power-of-two L, records in LDS, wave
+// path); the host groups cubes by instantiation.
 #include <hip/hip_runtime.h>
 
 #include "device.h"
