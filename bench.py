@@ -393,6 +393,17 @@ def main():
                          "mean_iterations": float(infos[:, 1].mean())},
         })
         log(f"batched: {ms:.3f} ms/step, {value:.0f} transforms/s, exact support {exact}/{B}")
+        # The same step replayed from the HIP graph (the other launch form).
+        gplan = F.Plan(specs, tuning=dict(tuning or {}, direct_launch=0))
+        gbound = gplan.bind(xs)
+        for _ in range(args.warmup):
+            gbound.run_batched()
+        torch.cuda.synchronize()
+        gms = event_time_ms(torch, gbound.run_batched, args.steps)
+        result["batched_graph"] = {"ms_per_step": round(gms, 4), "value": round(B / (gms * 1e-3), 1),
+                                   "unit": "transforms/s", "note": "the same step replayed from a HIP graph"}
+        log(f"batched, graph replay: {gms:.3f} ms/step")
+        del gbound, gplan
 
     if args.only in (None, "plain"):
         plain_all = bound.run_plain_all
@@ -423,7 +434,8 @@ def main():
         "config": {"workload": WORKLOAD, "global_batch": B, "parallelism": "single GPU",
                    "tuning": tuning or "library defaults"},
         "roofline": result["roofline"], "line_fft": result["line_fft"], "plain": result["plain"],
-        "accuracy": result["accuracy"], "line_fft_3d": result["line_fft_3d"], "configs": result["configs"],
+        "accuracy": result["accuracy"], "batched_graph": result["batched_graph"],
+        "line_fft_3d": result["line_fft_3d"], "configs": result["configs"],
     }
     if not args.no_cpu:
         log("CPU baseline (oracle)")
