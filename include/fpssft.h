@@ -127,7 +127,8 @@ typedef struct {
 /* Launch-shape choices of the autotuner (0 = library default; chunk_iters
  * is taken as given when >= 0, so pass -1 for its default).
  *  block_threads  threads per work-group of the solve and adjoint kernels
- *                 (64..512, multiple of 64)
+ *                 (64..512, multiple of 64); for D >= 3 the solve kernels
+ *                 use at least 64 (D+3), room for two peeling waves
  *  max_radix      largest FFT radix used for power-of-two factors (2, 4, 8)
  *  chunk_iters    iterations the plain path gathers and transforms ahead
  *                 in parallel before its sequential decode (>= 0)

@@ -155,6 +155,9 @@ class Plan:
         B.check(B.lib().fpssft_plan_create(descs, len(self.specs), C.byref(tn) if tn else None, C.byref(h)),
                 "plan_create")
         self._h = h
+        # kept with the plan: at interpreter exit the module's globals may be
+        # gone before the plan is collected
+        self._destroy = B.lib().fpssft_plan_destroy
         self.tuning = tuning
         self.info = []
         for c in range(len(self.specs)):
@@ -164,8 +167,9 @@ class Plan:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h is not None and h.value:
-            B.lib().fpssft_plan_destroy(h)
+        destroy = getattr(self, "_destroy", None)
+        if h is not None and h.value and destroy is not None:
+            destroy(h)
             self._h = None
 
     def close(self):

@@ -102,3 +102,19 @@ def test_plan_limits(setup):
         with pytest.raises(F.FpsSftError) as e:
             F.Plan([spec_for(F, (64, 64), 1)], tuning=tn)
         assert e.value.status == INVALID, tn
+
+
+def test_plan_alive_at_interpreter_exit_is_destroyed_cleanly():
+    """A plan still referenced when the interpreter exits is destroyed
+    without an error from its destructor (one child process)."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "import paper_1711_11407_amd as F\n"
+            "keep = F.Plan([F.CubeSpec((64, 64), seed=1)])\n"
+            "print('plan ok', flush=True)\n" % root)
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=100)
+    assert r.returncode == 0 and "plan ok" in r.stdout, r.stderr
+    assert "Exception ignored" not in r.stderr, r.stderr

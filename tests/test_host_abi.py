@@ -131,3 +131,4 @@ def test_tuning_cache_roundtrip(tmp_path):
     assert tune.load("gfx950", "batched", path) == out["tuning"]
     assert tune.load("gfx942", "batched", path) == dict(block_threads=64)
     assert tune.load("gfx950", "other", path) is None
+
