@@ -241,6 +241,42 @@ def lines_3d(torch, F, dev, args):
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4), "algorithmic_bytes": int(alg)}
 
 
+def differentiable(torch, F, W, dev, args):
+    """The differentiation workload: 64 cubes of 256 x 256, K = 50. One
+    step is the batched forward solve and the batched adjoint of
+    l = sum |a|^2 (grad_a = 2 a) into per-cube gradient cubes, which the
+    adjoint overwrites (zero fill included)."""
+    cubes = W.cfg5()
+    specs = [F.CubeSpec(c.dims, seed=c.schedule_seed, max_k=128, **W.NOISELESS_THRESH) for c in cubes]
+    plan = F.Plan(specs, tuning=load_tuning("batched"))
+    xs = [torch.from_numpy(c.x).to(dev) for c in cubes]
+    bound = plan.bind(xs)
+    outs = bound.outs
+    gxs = [torch.empty_like(x) for x in xs]
+    bound.run_batched()
+    torch.cuda.synchronize()
+    gas = [2 * o.amps for o in outs]
+
+    def bwd():
+        plan.amp_backward_batched(outs, gas, gxs)
+
+    def step():
+        bound.run_batched()
+        bwd()
+
+    for _ in range(max(1, args.warmup)):
+        step()
+    torch.cuda.synchronize()
+    reps = max(3, args.steps)
+    f_ms = event_time_ms(torch, bound.run_batched, reps)
+    b_ms = event_time_ms(torch, bwd, reps)
+    s_ms = event_time_ms(torch, step, reps)
+    log(f"differentiable: forward {f_ms:.3f} ms, adjoint {b_ms:.3f} ms, both {s_ms:.3f} ms for {len(cubes)} cubes")
+    return {"workload": "64 x 256^2 cubes, K = 50, l = sum |a|^2", "cubes": len(cubes),
+            "forward_ms": round(f_ms, 4), "adjoint_ms": round(b_ms, 4), "step_ms": round(s_ms, 4),
+            "steps_per_s": round(1e3 / s_ms, 1)}
+
+
 def per_config(torch, F, W, dev, args, with_oracle=True):
     """The single-cube workloads on the plain path (one fpssft_execute each,
     events around repeated calls) beside the FP64 oracle on one host core
@@ -282,7 +318,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--only", choices=["copy", "lines", "lines3d", "batched", "plain", "configs"], default=None)
+    ap.add_argument("--only", choices=["copy", "lines", "lines3d", "batched", "plain", "configs", "grad"],
+                    default=None)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--traffic-from", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
                     help="write profiles/traffic.json from rocprofv3 --pmc output directories")
@@ -422,6 +459,9 @@ def main():
     if args.only in (None, "configs"):
         result["configs"] = per_config(torch, F, W, dev, args, with_oracle=not args.no_cpu)
 
+    if args.only in (None, "grad"):
+        result["differentiable"] = differentiable(torch, F, W, dev, args)
+
     if args.only is not None:
         log(json.dumps(result))
         return
@@ -436,6 +476,7 @@ def main():
         "roofline": result["roofline"], "line_fft": result["line_fft"], "plain": result["plain"],
         "accuracy": result["accuracy"], "batched_graph": result["batched_graph"],
         "line_fft_3d": result["line_fft_3d"], "configs": result["configs"],
+        "differentiable": result["differentiable"],
     }
     if not args.no_cpu:
         log("CPU baseline (oracle)")
