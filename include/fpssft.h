@@ -258,8 +258,8 @@ fpssft_status fpssft_lines_fft_all(fpssft_plan_t plan, const void* const* xs,
  * grad_amps: device complex64 [max_k] (entries past k ignored); grad_x:
  * device complex64 cube, overwritten (zero off the sampled lines).
  * UNSUPPORTED for FPSSFT_FLAG_AMP_AVERAGE plans, and when a cube's line
- * cotangent, FFT scratch and twiddles plus its record cotangents and
- * iterations (24 L + 12 max_k bytes) exceed 160 KB of LDS. */
+ * cotangent, FFT scratch and twiddles plus its record cotangents
+ * (24 L + 8 max_k bytes) exceed 160 KB of LDS. */
 fpssft_status fpssft_amp_backward(fpssft_plan_t plan, int32_t cube,
                                   const fpssft_out* fwd, const void* grad_amps,
                                   void* grad_x, void* stream);
