@@ -252,13 +252,10 @@ def differentiable(torch, F, W, dev, args):
     xs = [torch.from_numpy(c.x).to(dev) for c in cubes]
     bound = plan.bind(xs)
     outs = bound.outs
-    gxs = [torch.empty_like(x) for x in xs]
     bound.run_batched()
     torch.cuda.synchronize()
-    gas = [2 * o.amps for o in outs]
-
-    def bwd():
-        plan.amp_backward_batched(outs, gas, gxs)
+    bound.bind_backward([(2 * o.amps).contiguous() for o in outs])
+    bwd = bound.run_backward
 
     def step():
         bound.run_batched()

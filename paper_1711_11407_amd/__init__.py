@@ -351,6 +351,31 @@ class Bound:
                 B.check(st, "execute")
         return self.outs
 
+    def bind_backward(self, grad_amps, grad_xs=None):
+        """Fix the amplitude cotangents (complex64 CUDA tensors of max_k
+        entries, one per cube) and the gradient cubes for run_backward."""
+        torch = _torch()
+        if len(grad_amps) != len(self.plan):
+            raise ValueError("one cotangent per cube")
+        for c, g in enumerate(grad_amps):
+            if not (g.is_cuda and g.dtype == torch.complex64 and g.is_contiguous()
+                    and g.numel() == self.plan.specs[c].max_k):
+                raise ValueError("grad_amps[c] must be a contiguous complex64 CUDA tensor of max_k entries")
+        if grad_xs is None:
+            grad_xs = [torch.empty_like(x) for x in self.xs]
+        self.grad_amps, self.grad_xs = list(grad_amps), list(grad_xs)
+        self._gp = (C.c_void_p * len(self.plan))(*[g.data_ptr() for g in self.grad_amps])
+        self._gxp = (C.c_void_p * len(self.plan))(*[g.data_ptr() for g in self.grad_xs])
+        self._fn_bw = B.lib().fpssft_amp_backward_batched
+        return self.grad_xs
+
+    def run_backward(self, stream=None):
+        """fpssft_amp_backward_batched on the bound outputs, cotangents and
+        gradient cubes (bind_backward first)."""
+        B.check(self._fn_bw(self.plan._h, self._op, self._gp, self._gxp, _stream_ptr(stream)),
+                "amp_backward_batched")
+        return self.grad_xs
+
 
 # ---------------------------------------------------------------------------
 # Differentiable amplitudes

@@ -96,3 +96,23 @@ def test_cfg5_batched_backward(F):
         single = plan.execute(c, xs[c].detach())
         g1 = plan.amp_backward(c, single, 2 * single.amps).cpu().numpy()
         np.testing.assert_allclose(g1, g, rtol=0, atol=1e-5 * np.abs(g).max())
+
+
+def test_bound_backward_equals_plan_backward(F):
+    """The pre-marshalled batched adjoint (Bound.run_backward) gives the same
+    gradients as Plan.amp_backward_batched, over repeated calls."""
+    import torch
+    dev = torch.device("cuda", 0)
+    cubes = [W.plant((64, 64), 10 + 5 * i, seed=70 + i) for i in range(6)]
+    specs = [spec_for(F, c.dims, c.schedule_seed, max_k=64) for c in cubes]
+    plan = F.Plan(specs)
+    xs = [torch.from_numpy(c.x).to(dev) for c in cubes]
+    bound = plan.bind(xs)
+    outs = bound.run_batched()
+    gas = [(2 * o.amps).contiguous() for o in outs]
+    ref = [g.cpu().numpy() for g in plan.amp_backward_batched(outs, gas)]
+    bound.bind_backward(gas)
+    for _ in range(3):
+        got = [g.cpu().numpy() for g in bound.run_backward()]
+        for a, b in zip(got, ref):
+            np.testing.assert_array_equal(a, b)
