@@ -422,7 +422,10 @@ def main():
             "roofline": {"kernel": "k_solve_batched", "bound": "hbm", "achieved": round(gbs, 2),
                          "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 5),
                          "traffic": traffic_for("k_solve_batched"), "algorithmic_bytes": int(alg),
-                         "note": "latency-bound: each cube's iterations are sequential"},
+                         "note": "algorithmic bytes are the sampled values; each random 8-byte sample costs a "
+                                 "128-byte HBM line (traffic), so the launch is HBM-bound in real bytes while "
+                                 "many cubes run and latency-bound in its tail, where a few dense cubes run "
+                                 "their sequential iterations"},
             "accuracy": {"exact_support_fraction": round(exact / B, 4), "exact_cubes": exact,
                          "mean_iterations": float(infos[:, 1].mean())},
         })
