@@ -195,7 +195,8 @@ fpssft_status fpssft_schedule_generate(const fpssft_desc* desc, int32_t T,
 fpssft_status fpssft_plan_create(const fpssft_desc* descs, int32_t batch,
                                  const fpssft_tuning* tuning, fpssft_plan_t* plan);
 
-/* Release the plan and its device memory (waits for the device). */
+/* Release the plan and its device memory (waits for the plan's device; the
+ * caller's current device is left as it was). */
 fpssft_status fpssft_plan_destroy(fpssft_plan_t plan);
 
 /* Host copy of cube `cube`'s schedule, int32 [T_max][2][ndim]. */
@@ -217,7 +218,9 @@ int64_t fpssft_plan_spectra_elems(fpssft_plan_t plan);
 /* Errors of the calls below, returned before anything is enqueued:
  * INVALID_ARG for a NULL plan, input, output or gradient pointer (every
  * pointer field of an fpssft_out included), a cube index outside
- * [0, batch), or an iteration range outside [0, T_max); UNSUPPORTED as
+ * [0, batch), an iteration range outside [0, T_max), or a current HIP
+ * device other than the plan's (the calls enqueue on the current device,
+ * and the plan's buffers live on its own); UNSUPPORTED as
  * stated per call. HIP errors while enqueueing return FPSSFT_ERR_HIP.
  * Algorithmic outcomes (OK, INCOMPLETE, CAPACITY) are not errors: they go
  * to info[2] on the device. The calls do not synchronize the stream. */

@@ -322,6 +322,8 @@ fpssft::KernelKey key_of(const fpssft_plan_t p, int c) {
 
 void destroy_plan(fpssft_plan_t p) {
   if (!p) return;
+  int prev = -1;
+  const bool restore = hipGetDevice(&prev) == hipSuccess && prev != p->device;
   hipSetDevice(p->device);
   hipDeviceSynchronize();
   if (p->gexec) hipGraphExecDestroy(p->gexec);
@@ -342,6 +344,14 @@ void destroy_plan(fpssft_plan_t p) {
   hipFree(p->d_ranges);
   hipFree(p->d_lqueue);
   delete p;
+  if (restore) hipSetDevice(prev);
+}
+
+// The hot-path calls enqueue on the current device: it must be the plan's,
+// or its device pointers would be used on another GPU.
+bool on_plan_device(const fpssft_plan_t p) {
+  int d = -1;
+  return hipGetDevice(&d) == hipSuccess && d == p->device;
 }
 
 fpssft_status build_plan(const fpssft_desc* descs, int32_t batch, const fpssft_tuning* tuning,
@@ -676,6 +686,7 @@ int64_t fpssft_plan_spectra_elems(fpssft_plan_t p) { return p ? p->spec_elems : 
 fpssft_status fpssft_execute(fpssft_plan_t p, int32_t cube, const void* x, const fpssft_out* out,
                              void* stream) {
   if (!p || cube < 0 || cube >= p->B || !x || !check_out(out)) return FPSSFT_ERR_INVALID_ARG;
+  if (!on_plan_device(p)) return FPSSFT_ERR_INVALID_ARG;
   hipStream_t st = (hipStream_t)stream;
   const CubeDesc& cd = p->descs[cube];
   const fpssft::KernelKey key = key_of(p, cube);
@@ -693,6 +704,7 @@ fpssft_status fpssft_execute(fpssft_plan_t p, int32_t cube, const void* x, const
 fpssft_status fpssft_execute_batched(fpssft_plan_t p, const void* const* xs, const fpssft_out* outs,
                                      void* stream) {
   if (!p || !xs || !outs) return FPSSFT_ERR_INVALID_ARG;
+  if (!on_plan_device(p)) return FPSSFT_ERR_INVALID_ARG;
   std::vector<OutPtrs> op(p->B);
   for (int c = 0; c < p->B; ++c) {
     if (!xs[c] || !check_out(&outs[c])) return FPSSFT_ERR_INVALID_ARG;
@@ -741,6 +753,7 @@ fpssft_status fpssft_execute_batched(fpssft_plan_t p, const void* const* xs, con
 fpssft_status fpssft_lines_fft(fpssft_plan_t p, int32_t cube, const void* x, int32_t t0, int32_t count,
                                void* spectra, void* stream) {
   if (!p || cube < 0 || cube >= p->B || !x || !spectra) return FPSSFT_ERR_INVALID_ARG;
+  if (!on_plan_device(p)) return FPSSFT_ERR_INVALID_ARG;
   const CubeDesc& cd = p->descs[cube];
   if (t0 < 0 || count < 0 || (int64_t)t0 + count > cd.T) return FPSSFT_ERR_INVALID_ARG;
   if (count == 0) return FPSSFT_OK;
@@ -752,6 +765,7 @@ fpssft_status fpssft_lines_fft(fpssft_plan_t p, int32_t cube, const void* x, int
 
 fpssft_status fpssft_lines_fft_all(fpssft_plan_t p, const void* const* xs, void* spectra, void* stream) {
   if (!p || !xs || !spectra) return FPSSFT_ERR_INVALID_ARG;
+  if (!on_plan_device(p)) return FPSSFT_ERR_INVALID_ARG;
   for (int c = 0; c < p->B; ++c)
     if (!xs[c]) return FPSSFT_ERR_INVALID_ARG;
   hipStream_t st = (hipStream_t)stream;
@@ -770,6 +784,7 @@ fpssft_status fpssft_lines_fft_all(fpssft_plan_t p, const void* const* xs, void*
 fpssft_status fpssft_amp_backward(fpssft_plan_t p, int32_t cube, const fpssft_out* fwd, const void* grad_amps,
                                   void* grad_x, void* stream) {
   if (!p || cube < 0 || cube >= p->B || !check_out(fwd) || !grad_amps || !grad_x) return FPSSFT_ERR_INVALID_ARG;
+  if (!on_plan_device(p)) return FPSSFT_ERR_INVALID_ARG;
   const CubeDesc& cd = p->descs[cube];
   // the adjoint follows the line-0 amplitude of Eq. decoding
   if (bwd_lds_bytes(cd) > p->lds_max || (cd.flags & FPS_AMP_AVERAGE)) return FPSSFT_ERR_UNSUPPORTED;
@@ -783,6 +798,7 @@ fpssft_status fpssft_amp_backward(fpssft_plan_t p, int32_t cube, const fpssft_ou
 fpssft_status fpssft_amp_backward_batched(fpssft_plan_t p, const fpssft_out* fwds, const void* const* grad_amps,
                                           void* const* grad_xs, void* stream) {
   if (!p || !fwds || !grad_amps || !grad_xs) return FPSSFT_ERR_INVALID_ARG;
+  if (!on_plan_device(p)) return FPSSFT_ERR_INVALID_ARG;
   std::vector<OutPtrs> op(p->B);
   std::vector<int64_t> lens(p->B);
   for (int c = 0; c < p->B; ++c) {
