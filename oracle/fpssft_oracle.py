@@ -11,7 +11,7 @@ the paper in its own order and notation:
 
   * line length L = LCM(N_0..N_{D-1}), c_k = L / N_k       (Lemma 1; Sec. 2.3)
   * slope set A: gcd(c_0 a_0, ..., c_{D-1} a_{D-1}) = 1   (Lemma 2; D > 2 is
-    this build's reading of the Multi-dimensional extension paragraph)
+    a reading of the Multi-dimensional extension paragraph)
   * per-iteration random slope and offset                  (Sec. 2.2)
   * D+1 lines: offset tau, and tau + e_{i-1} for line i    (Sec. 2.2, Eq.
     decoding, and the Multi-dimensional extension)
