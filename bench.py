@@ -325,7 +325,7 @@ def main():
         summarize_counters(args.traffic_from)
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build measures one GPU only: independent cubes shard across "
+        print(json.dumps({"error": "this benchmark measures one GPU only: independent cubes shard across "
                                    "GPUs with no exchange, and no multi-GPU path is built"}))
         sys.exit(2)
 

@@ -44,7 +44,7 @@ typedef enum {
   FPSSFT_INCOMPLETE = 1,      /* device outcome: T_max reached, residual != 0 */
   FPSSFT_CAPACITY = 2,        /* device outcome: max_k records, more found    */
   FPSSFT_ERR_INVALID_ARG = -1,
-  FPSSFT_ERR_UNSUPPORTED = -2, /* valid, but beyond this build (LDS, 32-bit) */
+  FPSSFT_ERR_UNSUPPORTED = -2, /* valid, but beyond the library (LDS, 32-bit) */
   FPSSFT_ERR_HIP = -3,         /* a HIP runtime call failed                   */
   FPSSFT_ERR_NOMEM = -4,
   FPSSFT_ERR_NO_DEVICE = -5

@@ -82,7 +82,7 @@ def in_slope_set(alpha: Sequence[int], dims: Sequence[int]) -> bool:
 
     In 2-D the paper's set is {a0 coprime a1, a0 coprime c1, a1 coprime c0};
     with c0 coprime c1 (L is the LCM) that is gcd(c0 a0, c1 a1) = 1. For any
-    D this build uses gcd(c_0 a_0, ..., c_{D-1} a_{D-1}) = 1.
+    D the set used here is gcd(c_0 a_0, ..., c_{D-1} a_{D-1}) = 1.
     """
     c = c_factors(dims)
     g = 0

@@ -611,7 +611,7 @@ const char* fpssft_strerror(int32_t s) {
     case FPSSFT_INCOMPLETE: return "incomplete: iteration budget reached with a nonzero residual";
     case FPSSFT_CAPACITY: return "capacity: the record list is full";
     case FPSSFT_ERR_INVALID_ARG: return "invalid argument";
-    case FPSSFT_ERR_UNSUPPORTED: return "unsupported size for this build";
+    case FPSSFT_ERR_UNSUPPORTED: return "valid but unsupported by the library (LDS or index range)";
     case FPSSFT_ERR_HIP: return "HIP runtime error";
     case FPSSFT_ERR_NOMEM: return "out of device memory";
     case FPSSFT_ERR_NO_DEVICE: return "no HIP device";
