@@ -59,6 +59,10 @@ __device__ __forceinline__ void ld_g_pair(const float2* p, int64_t i, float2& u,
   u = make_float2(q.x, q.y);
   v = make_float2(q.z, q.w);
 }
+// Elements i and i+1 in one 16-byte store (8-byte aligned).
+__device__ __forceinline__ void st_g_pair(float2* p, int64_t i, float2 u, float2 v) {
+  *(FPS_GLOBAL fps_f4a8*)((FPS_GLOBAL char*)p + i * 8) = fps_f4a8{u.x, u.y, v.x, v.y};
+}
 __device__ __forceinline__ void st_gi(int32_t* p, int64_t i, int32_t v) { ((FPS_GLOBAL int32_t*)p)[i] = v; }
 
 // x mod n for x < 2^32 (n a power of two when kPow2).

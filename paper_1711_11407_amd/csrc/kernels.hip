@@ -131,8 +131,11 @@ __device__ __forceinline__ void lines_item(const CubeDesc& cd, const float2* __r
     // Next iteration's gathers go out after the transform (scattered loads in
     // flight slow the LDS traffic of the butterflies).
     if (use_pf && i + 1 < tc) prefetch_issue<D, kPow2>(pf, g, x, sch + (i + 1) * 2 * D, nullptr, false);
+    // Two elements per lane and store: half the store instructions.
     float2* o = out + (int64_t)i * (D + 1) * L;
-    for (uint32_t e = threadIdx.x; e < (D + 1) * L; e += B) st_g(o, e, S[e]);
+    const uint32_t n = (D + 1) * L;
+    for (uint32_t e = 2 * threadIdx.x; e + 1 < n; e += 2 * B) st_g_pair(o, e, S[e], S[e + 1]);
+    if ((n & 1u) && threadIdx.x == 0) st_g(o, n - 1, S[n - 1]);
     lds_barrier();
   }
 }
