@@ -133,11 +133,13 @@ def test_deadlock_axis_schedule(F):
     assert got["status"] == O.STATUS_OK and got["k"] == 4
 
 
-@pytest.mark.parametrize("dims", [(64, 64), (16, 24), (128, 128, 128), (6, 10), (4, 6, 10, 2), (256, 512)])
+@pytest.mark.parametrize("dims", [(64, 64), (16, 24), (128, 128, 128), (6, 10), (4, 6, 10, 2), (256, 512),
+                                  (15, 21), (3, 5, 7, 3)])
 def test_lines_fft_matches_oracle_line_dft(F, dims):
     """Eq. sample_slice + Eq. hs: every gathered line's 1/L DFT, fp32 vs fp64
     on the same complex64 cube, relative max error <= 1e-5 of the line's
-    spectrum norm."""
+    spectrum norm. (15, 21) and (3, 5, 7, 3) give an odd number (D+1) L of
+    spectrum values per iteration."""
     torch, dev = torch_dev()
     x = W.random_dense(dims, 11).astype(np.complex64)
     spec = spec_for(F, dims, 5, max_iters=12)
@@ -155,8 +157,8 @@ def test_lines_fft_matches_oracle_line_dft(F, dims):
 
 def test_lines_fft_all_packed_layout(F):
     torch, dev = torch_dev()
-    shapes = [(64, 128), (32, 32), (16, 24)]
-    specs = [spec_for(F, d, 3 + i, max_iters=[20, 5, 9][i]) for i, d in enumerate(shapes)]
+    shapes = [(64, 128), (32, 32), (16, 24), (15, 21)]
+    specs = [spec_for(F, d, 3 + i, max_iters=[20, 5, 9, 7][i]) for i, d in enumerate(shapes)]
     plan = F.Plan(specs)
     xs = [torch.from_numpy(W.random_dense(d, i).astype(np.complex64)).to(dev) for i, d in enumerate(shapes)]
     allsp = plan.lines_fft_all(xs).cpu().numpy()
