@@ -41,7 +41,7 @@ def F():
     return F
 
 
-@pytest.mark.parametrize("seed", [11, 12])
+@pytest.mark.parametrize("seed", [11, 12, 13, 14, 15, 16])
 def test_random_problems_match_the_oracle(F, seed):
     torch, dev = torch_dev()
     cases = draw_cases(40, seed)
