@@ -26,13 +26,17 @@ the paper in its own order and notation:
   * frequency decode from phase differences, amplitude with the unshifted
     offset's phase removed                                 (Eq. decoding)
   * iteration cap T_max = floor(N / ((D+1) L))             (Sec. 3)
+  * the recovered set: distinct frequencies with nonzero amplitudes (the
+    set S of Eq. sigModel2); a frequency detected again later is merged into
+    its first record by summing amplitudes                 (Sec. 2.2)
 
 Readings taken where the paper is silent (thresholds, rounding, stopping,
 re-detection) are listed in the repository's design notes and in the
-docstrings below. Decisions that turn floating point into integers (the
-threshold tests, rint of the decoded phase) are taken in float32, the
-precision of the GPU kernels, on the oracle's fp64 residuals rounded to
-complex64; all other arithmetic is fp64.
+docstrings below. All arithmetic is fp64, the decisions included (threshold
+tests, the phase, rint of the decoded phase). The thresholds are the float32
+values the GPU plan receives, widened exactly to fp64. A float32 decision
+step (`Params.decision = "float32"`) exists only as a diagnostic, to measure
+how far the precision of the decisions matters on a workload.
 """
 from __future__ import annotations
 
@@ -234,53 +238,136 @@ class Params:
     amp_average: bool = False   # amplitude: mean over the D+1 lines of
                                 # r_i(m) exp(-j 2 pi sum m_k tau_k^(i) / N_k)
                                 # instead of line 0 alone (Eq. decoding)
+    decision: str = "float64"   # precision of the decisions; "float32" is a
+                                # diagnostic only (see decide_bins)
 
 
 @dataclasses.dataclass
 class Result:
-    freqs: np.ndarray      # int64 [k, D]
-    amps: np.ndarray       # complex128 [k]
-    rec_iter: np.ndarray   # int64 [k]: iteration that found the record
-    rec_bin: np.ndarray    # int64 [k]: its bin in that iteration's lines
-    iters: int             # iterations executed (lines gathered)
+    """The recovered set and the trace of the detections that produced it.
+
+    freqs/amps: the recovered set, distinct frequencies in the order of
+    their first detection; a frequency detected several times carries the
+    sum of its detections' amplitudes; a merged frequency whose amplitude
+    sum has |a| <= theta0 is not in the set (Eq. sigModel2 has a != 0) but in
+    dropped_freqs/dropped_amps. rec_*: one entry per detection, canonical
+    (iteration, bin) order; rec_sin[i] indexes concat(freqs, dropped_freqs).
+    """
+    freqs: np.ndarray          # int64 [k, D]
+    amps: np.ndarray           # complex128 [k]
+    rec_freqs: np.ndarray      # int64 [n, D]: decoded frequency of each detection
+    rec_amps: np.ndarray       # complex128 [n]: amplitude decoded at that detection
+    rec_iter: np.ndarray       # int64 [n]: iteration of the detection
+    rec_bin: np.ndarray        # int64 [n]: its bin in that iteration's lines
+    rec_sin: np.ndarray        # int64 [n]: index of its frequency in the set
+    dropped_freqs: np.ndarray  # int64 [kd, D]
+    dropped_amps: np.ndarray   # complex128 [kd]
+    iters: int                 # iterations executed (lines gathered)
     status: int
 
     @property
     def k(self) -> int:
         return len(self.amps)
 
+    @property
+    def n(self) -> int:
+        return len(self.rec_amps)
 
-_INV2PI_F32 = np.float32(1.0 / (2.0 * np.pi))
+
+def _threshold(v: float) -> float:
+    """A threshold as the plan's kernels receive it: rounded to float32."""
+    return float(np.float32(v))
 
 
 def decide_bins(r: np.ndarray, dims: Sequence[int], params: Params):
     """Per-bin 1-sparsity test and phase decode on one iteration's residual
     line spectra r [D+1, L] (Eq. decoding; magnitude equality as in Sec. 2.1).
 
-    The decisions are taken in float32: the residuals are rounded to
-    complex64 and the tests, the phase, u_k = N_k * phi * (1/2pi) and rint
-    (round half to even) are float32 operations.
+    fp64 throughout: magnitudes of the complex128 residuals, phi = atan2 of
+    r_{k+1}(m) conj(r_0(m)) in (-pi, pi], u_k = N_k phi / (2 pi), m_k =
+    rint(u_k) (round half to even) mod N_k, on-grid check |u_k - rint(u_k)|
+    <= gamma. The thresholds are the plan's float32 values.
+
+    params.decision == "float32" takes the same steps on the residuals
+    rounded to complex64 in float32 arithmetic; it is a diagnostic that
+    shows how close a workload's decisions are to the precision boundary,
+    not the reference.
     Returns (any_nonzero, candidate mask [L], decoded frequencies [L, D]).
     """
     D = len(dims)
-    r32 = r.astype(np.complex64)
-    mag = np.abs(r32).astype(np.float32)
-    th0 = np.float32(params.zero_thresh)
-    rho = np.float32(params.mag_rel_tol)
+    if params.decision == "float32":
+        rr = r.astype(np.complex64)
+        ft = np.float32
+    elif params.decision == "float64":
+        rr = np.asarray(r, dtype=np.complex128)
+        ft = np.float64
+    else:
+        raise ValueError("decision must be 'float64' or 'float32'")
+    mag = np.abs(rr).astype(ft)
+    th0 = ft(_threshold(params.zero_thresh))
+    rho = ft(_threshold(params.mag_rel_tol))
+    gtol = ft(_threshold(params.grid_tol))
+    inv2pi = ft(1.0 / (2.0 * np.pi))
     any_nonzero = bool((mag > th0).any())
     cand = mag[0] > th0
     for i in range(1, D + 1):
         cand &= np.abs(mag[i] - mag[0]) <= rho * mag[0]
     dec = np.zeros((r.shape[1], D), dtype=np.int64)
     for k in range(D):
-        z = r32[k + 1] * np.conj(r32[0])                       # complex64
-        phi = np.arctan2(z.imag, z.real).astype(np.float32)    # (-pi, pi]
-        u = (np.float32(dims[k]) * phi) * _INV2PI_F32
+        z = rr[k + 1] * np.conj(rr[0])
+        phi = np.arctan2(z.imag, z.real).astype(ft)            # (-pi, pi]
+        u = (ft(dims[k]) * phi) * inv2pi
         v = np.rint(u)
         if params.grid_tol >= 0:
-            cand &= np.abs(u - v) <= np.float32(params.grid_tol)
+            cand &= np.abs(u - v) <= gtol
         dec[:, k] = np.mod(v.astype(np.int64), int(dims[k]))
     return any_nonzero, cand, dec
+
+
+def merge_detections(rec_freqs: np.ndarray, rec_amps: np.ndarray, zero_thresh: float):
+    """The recovered set from the detection list (Sec. 2.2: the set of
+    recovered sinusoids; Eq. sigModel2: distinct frequencies, a != 0).
+
+    Frequencies in the order of their first detection; the amplitude of a
+    frequency is the sum of its detections' amplitudes, added in detection
+    order. A frequency detected more than once whose sum has |a| <= theta0
+    is dropped from the set. Returns (freqs, amps, dropped_freqs,
+    dropped_amps, rec_sin) with rec_sin indexing concat(freqs, dropped).
+    """
+    rec_freqs = np.asarray(rec_freqs, dtype=np.int64)
+    D = rec_freqs.shape[1] if rec_freqs.ndim == 2 else 0
+    first: dict = {}
+    order: list = []
+    sums: list = []
+    count: list = []
+    grp = np.zeros(len(rec_amps), dtype=np.int64)
+    for i, (f, a) in enumerate(zip(rec_freqs.tolist(), rec_amps)):
+        key = tuple(f)
+        if key not in first:
+            first[key] = len(order)
+            order.append(key)
+            sums.append(complex(a))
+            count.append(1)
+        else:
+            g = first[key]
+            sums[g] += complex(a)
+            count[g] += 1
+        grp[i] = first[key]
+    th0 = _threshold(zero_thresh)
+    keep = [count[g] == 1 or abs(sums[g]) > th0 for g in range(len(order))]
+    index = np.zeros(len(order), dtype=np.int64)
+    kept = [g for g in range(len(order)) if keep[g]]
+    dropped = [g for g in range(len(order)) if not keep[g]]
+    for i, g in enumerate(kept + dropped):
+        index[g] = i
+
+    def pack(gs):
+        return (np.array([order[g] for g in gs], dtype=np.int64).reshape(-1, D),
+                np.array([sums[g] for g in gs], dtype=np.complex128))
+
+    fk, ak = pack(kept)
+    fd, ad = pack(dropped)
+    return fk, ak, fd, ad, index[grp]
 
 
 def run(x: np.ndarray, alpha: np.ndarray, tau: np.ndarray,
@@ -300,10 +387,11 @@ def run(x: np.ndarray, alpha: np.ndarray, tau: np.ndarray,
          this bin), amplitude a = r_0(m) exp(-j 2 pi sum m_k tau_k / N_k)
          (or its mean over the D+1 lines, params.amp_average);
          append in bin order.
-    Re-detections are appended as further records (list semantics); the
-    construction-subtraction sums every record. A full list stops the run
-    with STATUS_CAPACITY after appending the candidates that fit, in bin
-    order.
+    Every detection is a further record of the list (a frequency found
+    again is one more term), and the construction-subtraction sums every
+    record; the output merges the list into the recovered set
+    (merge_detections). A full list (max_k detections) stops the run with
+    STATUS_CAPACITY after appending the candidates that fit, in bin order.
     """
     dims = [int(d) for d in x.shape]
     D = len(dims)
@@ -355,11 +443,13 @@ def run(x: np.ndarray, alpha: np.ndarray, tau: np.ndarray,
         if full:
             status, iters = STATUS_CAPACITY, t + 1
             break
-    return Result(freqs=np.array(rf, dtype=np.int64).reshape(-1, D),
-                  amps=np.array(ra, dtype=np.complex128),
+    rec_f = np.array(rf, dtype=np.int64).reshape(-1, D)
+    rec_a = np.array(ra, dtype=np.complex128)
+    fk, ak, fd, ad, rec_sin = merge_detections(rec_f, rec_a, params.zero_thresh)
+    return Result(freqs=fk, amps=ak, rec_freqs=rec_f, rec_amps=rec_a,
                   rec_iter=np.array(rt, dtype=np.int64),
-                  rec_bin=np.array(rm, dtype=np.int64),
-                  iters=iters, status=status)
+                  rec_bin=np.array(rm, dtype=np.int64), rec_sin=rec_sin,
+                  dropped_freqs=fd, dropped_amps=ad, iters=iters, status=status)
 
 
 # ---------------------------------------------------------------------------
@@ -367,22 +457,23 @@ def run(x: np.ndarray, alpha: np.ndarray, tau: np.ndarray,
 # ---------------------------------------------------------------------------
 
 
-def replay_amplitudes(x: np.ndarray, freqs: np.ndarray, rec_iter: np.ndarray,
+def replay_amplitudes(x: np.ndarray, rec_freqs: np.ndarray, rec_iter: np.ndarray,
                       rec_bin: np.ndarray, alpha: np.ndarray, tau: np.ndarray) -> np.ndarray:
-    """Recompute every record's amplitude from samples x with the decisions
-    (frequencies, iteration, bin) of a previous run held fixed.
+    """Recompute every detection's amplitude from samples x with the
+    decisions (frequency, iteration, bin of each detection) of a previous run
+    held fixed.
 
-    For each iteration that produced records, in order: gather line 0,
-    subtract the time-domain construction of the records of earlier
+    For each iteration that produced detections, in order: gather line 0,
+    subtract the time-domain construction of the detections of earlier
     iterations (with their replayed amplitudes), take the line DFT and read
-    each record's bin, removing the unshifted offset's phase (Eq. decoding).
-    The map x -> amplitudes is linear, so its gradient is exact.
+    each detection's bin, removing the unshifted offset's phase (Eq.
+    decoding). The map x -> amplitudes is linear, so its gradient is exact.
     """
     dims = [int(d) for d in x.shape]
     D = len(dims)
     L = line_length(dims)
     x64 = np.asarray(x).astype(np.complex128)
-    freqs = np.asarray(freqs, dtype=np.int64).reshape(-1, D)
+    freqs = np.asarray(rec_freqs, dtype=np.int64).reshape(-1, D)
     out = np.zeros(len(freqs), dtype=np.complex128)
     for t in sorted(set(int(v) for v in rec_iter)):
         a_vec = [int(v) for v in alpha[t]]
@@ -400,9 +491,26 @@ def replay_amplitudes(x: np.ndarray, freqs: np.ndarray, rec_iter: np.ndarray,
     return out
 
 
+def set_amplitudes(rec_amps: np.ndarray, rec_sin: np.ndarray, k: int) -> np.ndarray:
+    """Amplitudes of the k frequencies of the recovered set from the
+    detections' amplitudes: the sum over each frequency's detections, in
+    detection order (the merge of merge_detections, decisions fixed)."""
+    out = np.zeros(k, dtype=np.complex128)
+    for a, g in zip(rec_amps, np.asarray(rec_sin, dtype=np.int64)):
+        if g < k:
+            out[g] += a
+    return out
+
+
+def replay_set(x: np.ndarray, res: Result, alpha, tau) -> np.ndarray:
+    """The recovered set's amplitudes as a function of x, decisions fixed."""
+    a = replay_amplitudes(x, res.rec_freqs, res.rec_iter, res.rec_bin, alpha, tau)
+    return set_amplitudes(a, res.rec_sin, res.k)
+
+
 def touched_positions(dims, rec_iter, alpha, tau) -> np.ndarray:
     """Flat indices of the line-0 samples of every iteration that produced a
-    record: the only samples the amplitudes depend on."""
+    detection: the only samples the amplitudes depend on."""
     dims = [int(d) for d in dims]
     L = line_length(dims)
     pos = []
@@ -416,12 +524,13 @@ def touched_positions(dims, rec_iter, alpha, tau) -> np.ndarray:
 
 def grad_sum_abs2_fd(x: np.ndarray, res: Result, alpha, tau, positions=None,
                      h: float = 1.0) -> np.ndarray:
-    """Gradient of l(x) = sum_i |a_i(x)|^2 (amplitudes replayed with the
-    decisions of `res` fixed) by central finite differences in fp64,
-    in PyTorch's convention dl/dRe + j dl/dIm. l is quadratic in (Re x,
-    Im x), so central differences are exact up to rounding for any h.
-    Only `positions` (default: the touched line samples) are probed; every
-    other sample has zero gradient because no amplitude reads it."""
+    """Gradient of l(x) = sum_i |a_i(x)|^2 over the recovered set (amplitudes
+    replayed with the decisions of `res` fixed) by central finite
+    differences in fp64, in PyTorch's convention dl/dRe + j dl/dIm. l is
+    quadratic in (Re x, Im x), so central differences are exact up to
+    rounding for any h. Only `positions` (default: the touched line samples)
+    are probed; every other sample has zero gradient because no amplitude
+    reads it."""
     dims = x.shape
     x64 = np.asarray(x).astype(np.complex128)
     if positions is None:
@@ -429,8 +538,7 @@ def grad_sum_abs2_fd(x: np.ndarray, res: Result, alpha, tau, positions=None,
     g = np.zeros(int(np.prod(dims)), dtype=np.complex128)
 
     def loss(xx):
-        a = replay_amplitudes(xx, res.freqs, res.rec_iter, res.rec_bin, alpha, tau)
-        return float(np.sum(np.abs(a) ** 2))
+        return float(np.sum(np.abs(replay_set(xx, res, alpha, tau)) ** 2))
 
     flat = x64.reshape(-1)
     for n in positions:
@@ -444,14 +552,13 @@ def grad_sum_abs2_fd(x: np.ndarray, res: Result, alpha, tau, positions=None,
 
 
 def amp_matrix(x_shape, res: Result, alpha, tau, positions) -> np.ndarray:
-    """Columns of the linear map M (amplitudes = M x) at the given flat
+    """Columns of the linear map M (set amplitudes = M x) at the given flat
     positions, by replaying unit impulses: M[:, j] = replay(e_{positions[j]})."""
     N = int(np.prod(x_shape))
     cols = []
     for n in positions:
         e = np.zeros(N, dtype=np.complex128); e[n] = 1.0
-        cols.append(replay_amplitudes(e.reshape(x_shape), res.freqs, res.rec_iter,
-                                      res.rec_bin, alpha, tau))
+        cols.append(replay_set(e.reshape(x_shape), res, alpha, tau))
     return np.stack(cols, axis=1) if cols else np.zeros((res.k, 0), np.complex128)
 
 

@@ -371,12 +371,13 @@ def _fixed_run(dims, K, seed):
 def test_replay_reproduces_the_run_and_is_linear():
     x, al, ta, res = _fixed_run((32, 48), 60, 21)
     assert len(set(res.rec_iter.tolist())) >= 2
-    rep = O.replay_amplitudes(x, res.freqs, res.rec_iter, res.rec_bin, al, ta)
-    np.testing.assert_allclose(rep, res.amps, atol=1e-12)
+    rep = O.replay_amplitudes(x, res.rec_freqs, res.rec_iter, res.rec_bin, al, ta)
+    np.testing.assert_allclose(rep, res.rec_amps, atol=1e-12)
+    np.testing.assert_allclose(O.replay_set(x, res, al, ta), res.amps, atol=1e-12)
     rng = np.random.default_rng(0)
     y = rng.standard_normal(x.shape) + 1j * rng.standard_normal(x.shape)
     z = rng.standard_normal(x.shape) + 1j * rng.standard_normal(x.shape)
-    f = lambda v: O.replay_amplitudes(v, res.freqs, res.rec_iter, res.rec_bin, al, ta)
+    f = lambda v: O.replay_amplitudes(v, res.rec_freqs, res.rec_iter, res.rec_bin, al, ta)
     np.testing.assert_allclose(f(2.5 * y - 1j * z), 2.5 * f(y) - 1j * f(z), atol=1e-11)
 
 
@@ -414,3 +415,102 @@ def test_fd_gradient_equals_conjugate_transpose_map():
     touched = O.touched_positions(x.shape, res.rec_iter, al, ta)
     off = np.setdiff1d(allpos, touched)
     assert np.all(g.reshape(-1)[off] == 0)
+
+
+# --------------------------------------------------------------------------
+# The recovered set: distinct frequencies, nonzero amplitudes (Eq. sigModel2)
+# --------------------------------------------------------------------------
+
+def test_merge_detections_by_hand():
+    """A frequency detected twice is one element of the set with the sum of
+    the amplitudes, at the position of its first detection; a sum at or
+    below theta0 leaves the set (a != 0) and is reported as dropped."""
+    a, b, c = 0.5 + 0.2j, -0.3 + 0.9j, 0.25 - 0.1j
+    f = np.array([[1, 2], [3, 4], [1, 2]])
+    fk, ak, fd, ad, sin = O.merge_detections(f, np.array([a, b, c]), 1e-3)
+    assert fk.tolist() == [[1, 2], [3, 4]] and len(fd) == 0
+    np.testing.assert_allclose(ak, [a + c, b], rtol=0, atol=1e-15)
+    assert sin.tolist() == [0, 1, 0]
+    f = np.array([[1, 2], [3, 4], [1, 2], [1, 2], [5, 6]])
+    fk, ak, fd, ad, sin = O.merge_detections(f, np.array([a, b, c, -(a + c) + 1e-6, 2.0]), 1e-3)
+    assert fk.tolist() == [[3, 4], [5, 6]] and fd.tolist() == [[1, 2]]
+    np.testing.assert_allclose(ak, [b, 2.0], rtol=0, atol=1e-15)
+    assert abs(ad[0] - 1e-6) < 1e-15
+    assert sin.tolist() == [2, 0, 2, 2, 1]       # the dropped frequency follows the set
+    # a single detection stays, whatever its amplitude
+    fk, ak, fd, ad, sin = O.merge_detections(np.array([[0, 1]]), np.array([1e-9]), 1e-3)
+    assert fk.tolist() == [[0, 1]] and len(fd) == 0
+
+
+def test_redetection_in_the_batched_workload_is_merged():
+    """Cube 148 of the batched workload (128 x 64, K = 275): a false
+    detection at iteration 5 is found again at iteration 6 with the opposite
+    amplitude. The set keeps the 275 planted frequencies; the false one
+    leaves it with an amplitude sum of rounding size. The detections' sum
+    per frequency equals the set's amplitudes (construction-subtraction of
+    the list and of the set agree: linearity)."""
+    cube = W.cfg4(only=[148])[0]
+    assert cube.dims == (128, 64) and len(cube.amps) == 275
+    al, ta = O.schedule(cube.dims, O.default_max_iters(cube.dims), cube.schedule_seed)
+    res = O.run(cube.x, al, ta, O.Params(**W.NOISELESS_THRESH, max_k=512))
+    assert res.status == O.STATUS_OK and res.n == 277 and res.k == 275
+    assert {tuple(f) for f in res.freqs.tolist()} == {tuple(f) for f in cube.freqs.tolist()}
+    assert res.dropped_freqs.tolist() == [[83, 46]] and abs(res.dropped_amps[0]) < 1e-5
+    twice = [i for i in range(res.n) if res.rec_freqs[i].tolist() == [83, 46]]
+    assert [int(res.rec_iter[i]) for i in twice] == [5, 6]
+    assert abs(res.rec_amps[twice[0]]) > 1.0
+    assert all(res.rec_sin[i] == res.k for i in twice)
+    total = np.zeros(res.k + 1, dtype=np.complex128)
+    np.add.at(total, res.rec_sin, res.rec_amps)
+    np.testing.assert_allclose(total[:res.k], res.amps, atol=1e-15)
+    want = {tuple(f): a for f, a in zip(cube.freqs.tolist(), cube.amps)}
+    assert max(abs(want[tuple(f)] - a) for f, a in zip(res.freqs.tolist(), res.amps)) < 1e-5
+    # replay reproduces the merged set (decisions fixed) and stays linear
+    x = cube.x.astype(np.complex128)
+    np.testing.assert_allclose(O.replay_set(x, res, al, ta), res.amps, atol=1e-12)
+
+
+def test_noisy_set_is_a_set():
+    """Under noise (20 dB) frequencies are found again; the output is still
+    a set of distinct frequencies with |a| > theta0 in the order of first
+    detection, and the detection amplitudes sum to it."""
+    cube = W.plant((128, 128), 60, seed=42, mag=(0.5, 1.5), snr_db=20.0)
+    th = W.cfg2_thresh(cube, 128)
+    al, ta = O.schedule(cube.dims, 42, cube.schedule_seed)
+    res = O.run(cube.x, al, ta, O.Params(**th, max_k=4096))
+    assert res.n > res.k + len(res.dropped_amps)           # some frequency found twice
+    keys = [tuple(f) for f in res.freqs.tolist()]
+    assert len(set(keys)) == len(keys)
+    assert np.all(np.abs(res.amps) > np.float32(th["zero_thresh"]))
+    first = {}
+    for i, f in enumerate(res.rec_freqs.tolist()):
+        first.setdefault(tuple(f), i)
+    pos = [first[k] for k in keys]
+    assert pos == sorted(pos)
+    total = np.zeros(res.k + len(res.dropped_amps), dtype=np.complex128)
+    np.add.at(total, res.rec_sin, res.rec_amps)
+    np.testing.assert_allclose(total[:res.k], res.amps, atol=1e-12)
+
+
+@pytest.mark.parametrize("case", ["cfg1", "cfg4_sample", "odd_shapes"])
+def test_float32_decisions_agree_on_the_workloads(case):
+    """The reference decides in fp64; the kernels decide in float32. On
+    these workloads a float32 decision step gives the same decisions, i.e.
+    no decision lies within float32 rounding of its threshold (the margins
+    of the default thresholds are 20x or more)."""
+    if case == "cfg1":
+        cubes = [W.cfg1()]
+    elif case == "cfg4_sample":
+        cubes = W.cfg4(only=range(0, 1024, 64))
+    else:
+        cubes = [W.plant(d, k, seed=s, mag=(0.5, 1.5)) for d, k, s in
+                 [((16, 24), 12, 1), ((6, 10), 3, 2), ((8, 8, 12), 20, 3), ((7, 9), 4, 4)]]
+    for c in cubes:
+        T = max(O.default_max_iters(c.dims), 30) if np.prod(c.dims) < 4096 else 0
+        T = T or O.default_max_iters(c.dims)
+        al, ta = O.schedule(c.dims, T, c.schedule_seed)
+        r64 = O.run(c.x, al, ta, O.Params(**W.NOISELESS_THRESH, max_iters=T, max_k=512))
+        r32 = O.run(c.x, al, ta, O.Params(**W.NOISELESS_THRESH, max_iters=T, max_k=512, decision="float32"))
+        assert (r64.status, r64.iters, r64.n) == (r32.status, r32.iters, r32.n)
+        np.testing.assert_array_equal(r64.rec_freqs, r32.rec_freqs)
+        np.testing.assert_array_equal(r64.rec_bin, r32.rec_bin)
