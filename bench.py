@@ -409,10 +409,13 @@ def main():
         exact = 0
         alg = 0
         for c in range(B):
-            k, iters, status = (int(v) for v in infos[c, :3])
+            k, iters, status, n, kd = (int(v) for v in infos[c, :5])
             D = len(specs[c].dims)
             L = plan.info[c][0]
-            alg += iters * (D + 1) * L * 8 + k * (4 * D + 16) + 16
+            # gathered samples; the set and its left-out merged entries
+            # (frequency + amplitude), the detection trace (iteration, bin,
+            # set index) and the info words written
+            alg += iters * (D + 1) * L * 8 + (k + kd) * (4 * D + 8) + n * 12 + 32
             if status == 0:
                 got = {tuple(f) for f in outs[c].freqs[:k].cpu().numpy().tolist()}
                 exact += got == {tuple(f) for f in cubes[c].freqs.tolist()}

@@ -36,7 +36,9 @@ extern "C" {
 #endif
 
 #define FPSSFT_MAX_D 4
-#define FPSSFT_ABI_VERSION 2
+#define FPSSFT_ABI_VERSION 3
+/* Words of fpssft_out.info. */
+#define FPSSFT_INFO_LEN 8
 
 /* Return codes (negative) and device-side outcomes (non-negative). */
 typedef enum {
@@ -97,30 +99,56 @@ typedef struct {
  *                 line 0; for noisy data the average has 1/(D+1) of the
  *                 variance). fpssft_amp_backward returns UNSUPPORTED.
  *  LITERAL_PEEL   construction-subtraction as the paper states it (Sec. 2.2):
- *                 the recovered records' line spectra are inverse transformed
- *                 and subtracted from the gathered samples before the line
- *                 DFT, instead of being subtracted from the line spectra.
- *                 Equal up to rounding; slower (two more transforms per
- *                 line). UNSUPPORTED together with lines too long for LDS. */
+ *                 the recovered sinusoids' line spectra are inverse
+ *                 transformed and subtracted from the gathered samples
+ *                 before the line DFT, instead of being subtracted from the
+ *                 line spectra. Equal up to rounding; slower (two more
+ *                 transforms per line). UNSUPPORTED together with lines too
+ *                 long for LDS.
+ *  DETERMINISTIC  bit-reproducible results. Every plan has them: the
+ *                 construction-subtraction sums each bin's contributions in
+ *                 64-bit fixed point, exact and independent of the order in
+ *                 which the work-group's threads meet them (no float
+ *                 atomics), so repeated calls on the same input give
+ *                 identical bits. The flag is accepted and changes nothing. */
 #define FPSSFT_FLAG_AXIS_SCHEDULE 0x1u
 #define FPSSFT_FLAG_AMP_AVERAGE 0x2u
 #define FPSSFT_FLAG_LITERAL_PEEL 0x4u
+#define FPSSFT_FLAG_DETERMINISTIC 0x8u
 
 /* Per-cube outputs: all DEVICE pointers, caller-owned.
- *  freqs     int32 [max_k][ndim]  recovered frequency indices m_k in [0, N_k)
- *  amps      complex64 [max_k]    recovered amplitudes a (Eq. decoding)
- *  rec_iter  int32 [max_k]        iteration that found each record
- *  rec_bin   int32 [max_k]        its bin m in that iteration's lines
- *  info      int32 [4]            k, iterations executed, outcome, reserved
- * Records are in canonical order: iteration ascending, bin ascending. A
- * frequency detected again in a later iteration is a further record (the
- * recovered set is a list; its construction sums all records). Entries past
- * info[0] are left unchanged. */
+ *
+ * The result is the recovered set of Sec. 2.2, i.e. the set S of Eq.
+ * sigModel2: distinct frequencies with nonzero amplitudes. Each iteration
+ * decodes some bins; every such decoding is a detection. A frequency
+ * detected again in a later iteration (a false detection in an earlier
+ * iteration leaves such a residue behind) is merged into its first record:
+ * its amplitude is the sum of its detections' amplitudes. A merged frequency
+ * whose sum has |a| <= theta0 is not part of the set; it is listed after the
+ * set (positions k .. k+kd-1) so that the detection trace stays complete.
+ *  freqs     int32 [max_k][ndim]  frequency indices m_k in [0, N_k): the
+ *                                 set (0..k-1) in the order of first
+ *                                 detection, then the merged frequencies
+ *                                 left out of it (k..k+kd-1), same order
+ *  amps      complex64 [max_k]    amplitudes a of the same entries
+ *                                 (Eq. decoding; sums of detections)
+ *  rec_iter  int32 [max_k]        detection i: iteration
+ *  rec_bin   int32 [max_k]        detection i: its bin m in that
+ *                                 iteration's lines
+ *  rec_sin   int32 [max_k]        detection i: index of its frequency in
+ *                                 freqs / amps (< k + kd)
+ *  info      int32 [FPSSFT_INFO_LEN]  k (set size), iterations executed,
+ *                                 outcome, n (detections), kd (merged
+ *                                 frequencies left out of the set), 0, 0, 0
+ * Detections are in canonical order: iteration ascending, bin ascending;
+ * max_k bounds the number of detections n (CAPACITY when more are found),
+ * hence also k + kd <= n. Entries past those counts are left unchanged. */
 typedef struct {
   int32_t* freqs;
   void* amps;
   int32_t* rec_iter;
   int32_t* rec_bin;
+  int32_t* rec_sin;
   int32_t* info;
 } fpssft_out;
 
@@ -190,10 +218,16 @@ fpssft_status fpssft_schedule_generate(const fpssft_desc* desc, int32_t T,
  * Lines whose D+1 spectra, a second buffer and the twiddles do not fit in
  * LDS (160 KB) are transformed one line at a time, with the twiddles read
  * from device memory; UNSUPPORTED when even the D+1 spectra plus one line of
- * scratch do not fit ((D+2) L * 8 bytes > 160 KB less the record list,
- * e.g. L > 5000 for D = 2). */
+ * scratch do not fit ((D+2) L * 8 bytes > 160 KB, e.g. L > 6800 for D = 2).
+ * A cube's record store (max_k slots of 28 + 4 D bytes: set entry and
+ * detection) stays in LDS when it fits beside the spectra, else the plan
+ * allocates it in device memory. */
 fpssft_status fpssft_plan_create(const fpssft_desc* descs, int32_t batch,
                                  const fpssft_tuning* tuning, fpssft_plan_t* plan);
+
+/* The plan of the problem statement (Sec. 2; the line design of Lemmas 1
+ * and 2): fpssft_plan_create with the library's default launch shapes. */
+fpssft_status fpssft_plan(const fpssft_desc* descs, int32_t batch, fpssft_plan_t* plan);
 
 /* Release the plan and its device memory (waits for the plan's device; the
  * caller's current device is left as it was). */
@@ -225,49 +259,64 @@ int64_t fpssft_plan_spectra_elems(fpssft_plan_t plan);
  * Algorithmic outcomes (OK, INCOMPLETE, CAPACITY) are not errors: they go
  * to info[2] on the device. The calls do not synchronize the stream. */
 
-/* Plain per-cube FPS-SFT on cube `cube` of the plan: the line gather + FFT
- * kernel transforms the first chunk of iterations in parallel, then one
- * work-group peels, tests, decodes and appends iteration by iteration,
- * gathering and transforming further lines itself when the chunk runs out.
- * x: device complex64 cube; out: device outputs (see fpssft_out). */
+/* Plain per-cube FPS-SFT on cube `cube` of the plan: the method of Sec.
+ * 2.2 with the Multi-dimensional extension, iteration by iteration until an
+ * empty residual or T_max (Sec. 3): gather the D+1 lines (Eq.
+ * sample_slice), take their 1/L DFTs (Eq. hs), subtract the recovered set
+ * (construction-subtraction, Eq. freqSum), test every bin for 1-sparsity,
+ * decode frequency and amplitude (Eq. decoding) and record. The line gather
+ * + FFT kernel transforms the first chunk of iterations in parallel, then
+ * one work-group runs the sequential part, gathering and transforming
+ * further lines itself when the chunk runs out.
+ * x: device complex64 cube, read only; out: device outputs (fpssft_out),
+ * written by the call. */
 fpssft_status fpssft_execute(fpssft_plan_t plan, int32_t cube, const void* x,
                              const fpssft_out* out, void* stream);
 
-/* All cubes of the plan in one persistent launch per kernel instantiation
- * (work-groups take cubes from a device queue, shortest lines first),
- * replayed from a HIP graph or launched directly (fpssft_tuning). xs: host
- * array of `batch` device cube pointers; outs: host array of `batch` output
- * structs. Results equal fpssft_execute's cube by cube. */
+/* The same method (Sec. 2.2) for all cubes of the plan in one persistent
+ * launch per kernel instantiation (work-groups take cubes from a device
+ * queue, shortest lines first), replayed from a HIP graph or launched
+ * directly (fpssft_tuning). xs: host array of `batch` device cube pointers;
+ * outs: host array of `batch` output structs (device pointers inside).
+ * Results equal fpssft_execute's cube by cube, bit for bit. */
 fpssft_status fpssft_execute_batched(fpssft_plan_t plan, const void* const* xs,
                                      const fpssft_out* outs, void* stream);
 
 /* Line gather + L-point DFT (Eq. sample_slice, Eq. hs) of iterations
- * t0..t0+count-1 of cube `cube`: spectra (device complex64) receives
- * [count][D+1][L], s_hat(alpha, tau^{(t,i)}, m) with the 1/L factor. */
+ * t0..t0+count-1 of cube `cube`: spectra (device complex64, caller-owned)
+ * receives [count][D+1][L], s_hat(alpha, tau^{(t,i)}, m) with the 1/L
+ * factor. */
 fpssft_status fpssft_lines_fft(fpssft_plan_t plan, int32_t cube, const void* x,
                                int32_t t0, int32_t count, void* spectra,
                                void* stream);
 
 /* The same for every cube over its whole budget t = 0..T_max-1, in one
- * launch, into the packed buffer (see fpssft_plan_cube_info). */
+ * launch, into the packed buffer (see fpssft_plan_cube_info). xs: host
+ * array of `batch` device cube pointers. */
 fpssft_status fpssft_lines_fft_all(fpssft_plan_t plan, const void* const* xs,
                                    void* spectra, void* stream);
 
-/* Adjoint of the amplitude estimates with the decisions of a forward run
- * held fixed (frequencies, iterations, bins: not differentiated). The
- * amplitudes are then linear in x, a = M x; this writes grad_x = M^H grad_a
+/* Adjoint of the set amplitudes of Eq. decoding with the decisions of a
+ * forward run held fixed (frequencies, iterations, bins, merges: not
+ * differentiated). This form is not in the paper; it is built on its
+ * amplitude estimate and construction-subtraction (Sec. 2.2), which make
+ * the amplitudes linear in x, a = M x. It writes grad_x = M^H grad_a
  * (PyTorch's complex convention: for real l, grad = dl/dRe + j dl/dIm).
  * fwd: the forward outputs of cube `cube` (records and info on device);
- * grad_amps: device complex64 [max_k] (entries past k ignored); grad_x:
- * device complex64 cube, overwritten (zero off the sampled lines).
- * UNSUPPORTED for FPSSFT_FLAG_AMP_AVERAGE plans, and when a cube's line
- * cotangent, FFT scratch and twiddles plus its record cotangents
- * (24 L + 8 max_k bytes) exceed 160 KB of LDS. */
+ * grad_amps: device complex64 [max_k], the cotangents of the entries
+ * 0..k+kd-1 of freqs/amps (the set and the merged frequencies left out of
+ * it, all sums of detections; later entries ignored); grad_x: device
+ * complex64 cube,
+ * overwritten (zero off the sampled lines). UNSUPPORTED for
+ * FPSSFT_FLAG_AMP_AVERAGE plans, and when a cube's line cotangent, FFT
+ * scratch and twiddles plus its detection cotangents (24 L + 8 max_k
+ * bytes) exceed 160 KB of LDS. */
 fpssft_status fpssft_amp_backward(fpssft_plan_t plan, int32_t cube,
                                   const fpssft_out* fwd, const void* grad_amps,
                                   void* grad_x, void* stream);
 
-/* The adjoint for every cube of the plan in one launch. */
+/* The adjoint for every cube of the plan in one launch: host arrays of
+ * `batch` forward outputs, cotangent pointers and gradient-cube pointers. */
 fpssft_status fpssft_amp_backward_batched(fpssft_plan_t plan,
                                           const fpssft_out* fwds,
                                           const void* const* grad_amps,

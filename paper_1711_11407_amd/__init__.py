@@ -7,7 +7,8 @@ kernels of libfpssft.so.
 
     plan = Plan([CubeSpec((256, 256), seed=3)])
     res = plan.execute(0, x)             # x: complex64 cuda tensor
-    res.k, res.freqs[:k], res.amps[:k]   # after res.sync()
+    h = res.host()                       # synchronises
+    h["k"], h["freqs"], h["amps"]        # the recovered set
 
 Differentiable amplitudes (frequencies fixed, not differentiated):
 
@@ -43,12 +44,14 @@ class CubeSpec:
     axis_schedule: bool = False  # generated slopes e_{t mod D} (FPSSFT_FLAG_AXIS_SCHEDULE)
     amp_average: bool = False    # amplitude averaged over the D+1 lines (FPSSFT_FLAG_AMP_AVERAGE)
     literal_peel: bool = False   # time-domain construction-subtraction (FPSSFT_FLAG_LITERAL_PEEL)
+    deterministic: bool = False  # FPSSFT_FLAG_DETERMINISTIC (every plan is bit-reproducible)
 
     @property
     def flags(self) -> int:
         return ((B.FLAG_AXIS_SCHEDULE if self.axis_schedule else 0)
                 | (B.FLAG_AMP_AVERAGE if self.amp_average else 0)
-                | (B.FLAG_LITERAL_PEEL if self.literal_peel else 0))
+                | (B.FLAG_LITERAL_PEEL if self.literal_peel else 0)
+                | (B.FLAG_DETERMINISTIC if self.deterministic else 0))
 
     def to_c(self):
         d = B.Desc()
@@ -103,13 +106,17 @@ def _stream_ptr(stream) -> C.c_void_p:
 
 @dataclasses.dataclass
 class Result:
-    """Device outputs of one cube (fpssft_out)."""
+    """Device outputs of one cube (fpssft_out): the recovered set (distinct
+    frequencies, amplitudes summed over their detections; entries k..k+kd-1
+    are merged frequencies whose sum vanished, left out of the set) and the
+    detection trace in canonical (iteration, bin) order."""
 
     freqs: "object"     # int32 [max_k, D]
     amps: "object"      # complex64 [max_k]
-    rec_iter: "object"  # int32 [max_k]
-    rec_bin: "object"   # int32 [max_k]
-    info: "object"      # int32 [4]: k, iterations, status, 0
+    rec_iter: "object"  # int32 [max_k]: detection -> iteration
+    rec_bin: "object"   # int32 [max_k]: detection -> bin
+    rec_sin: "object"   # int32 [max_k]: detection -> index in freqs/amps
+    info: "object"      # int32 [8]: k, iterations, status, n, kd, 0, 0, 0
 
     def c_out(self) -> B.Out:
         o = B.Out()
@@ -117,16 +124,21 @@ class Result:
         o.amps = self.amps.data_ptr()
         o.rec_iter = self.rec_iter.data_ptr()
         o.rec_bin = self.rec_bin.data_ptr()
+        o.rec_sin = self.rec_sin.data_ptr()
         o.info = self.info.data_ptr()
         return o
 
     def host(self) -> dict:
-        """Synchronise and copy the first k records to numpy."""
+        """Synchronise and copy the set (k entries), the merged frequencies
+        left out of it (kd) and the n detections to numpy."""
         info = self.info.cpu().numpy()
-        k = int(info[0])
-        return dict(k=k, iters=int(info[1]), status=int(info[2]),
-                    freqs=self.freqs[:k].cpu().numpy(), amps=self.amps[:k].cpu().numpy(),
-                    rec_iter=self.rec_iter[:k].cpu().numpy(), rec_bin=self.rec_bin[:k].cpu().numpy())
+        k, n, kd = int(info[0]), int(info[3]), int(info[4])
+        freqs = self.freqs[:k + kd].cpu().numpy()
+        amps = self.amps[:k + kd].cpu().numpy()
+        return dict(k=k, iters=int(info[1]), status=int(info[2]), n=n, kd=kd,
+                    freqs=freqs[:k], amps=amps[:k], dropped_freqs=freqs[k:], dropped_amps=amps[k:],
+                    rec_iter=self.rec_iter[:n].cpu().numpy(), rec_bin=self.rec_bin[:n].cpu().numpy(),
+                    rec_sin=self.rec_sin[:n].cpu().numpy())
 
 
 class Plan:
@@ -206,7 +218,8 @@ class Plan:
                       amps=torch.zeros(s.max_k, dtype=torch.complex64, device=dev),
                       rec_iter=torch.zeros(s.max_k, dtype=torch.int32, device=dev),
                       rec_bin=torch.zeros(s.max_k, dtype=torch.int32, device=dev),
-                      info=torch.zeros(4, dtype=torch.int32, device=dev))
+                      rec_sin=torch.zeros(s.max_k, dtype=torch.int32, device=dev),
+                      info=torch.zeros(B.INFO_LEN, dtype=torch.int32, device=dev))
 
     def _check_x(self, cube: int, x):
         torch = _torch()
@@ -438,7 +451,8 @@ def _fns():
 
 
 def sft_amplitudes(plan: Plan, cube: int, x):
-    """(amps [max_k] differentiable, freqs [max_k, D], info [4]) of one cube."""
+    """(amps [max_k] differentiable, freqs [max_k, D], info [8]) of one cube:
+    the recovered set is amps[:k], freqs[:k] with k = info[0]."""
     return _fns()[0].apply(x, plan, cube)
 
 

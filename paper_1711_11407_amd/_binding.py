@@ -12,8 +12,9 @@ import os
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_lib", "libfpssft.so")
 
 MAX_D = 4
-ABI_VERSION = 2
-FLAG_AXIS_SCHEDULE, FLAG_AMP_AVERAGE, FLAG_LITERAL_PEEL = 0x1, 0x2, 0x4
+ABI_VERSION = 3
+INFO_LEN = 8
+FLAG_AXIS_SCHEDULE, FLAG_AMP_AVERAGE, FLAG_LITERAL_PEEL, FLAG_DETERMINISTIC = 0x1, 0x2, 0x4, 0x8
 OK, INCOMPLETE, CAPACITY = 0, 1, 2
 ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_HIP, ERR_NOMEM, ERR_NO_DEVICE = -1, -2, -3, -4, -5
 
@@ -39,6 +40,7 @@ class Out(C.Structure):
         ("amps", C.c_void_p),
         ("rec_iter", C.c_void_p),
         ("rec_bin", C.c_void_p),
+        ("rec_sin", C.c_void_p),
         ("info", C.c_void_p),
     ]
 
@@ -62,6 +64,7 @@ SIGNATURES = [
     ("fpssft_validate", C.c_int32, [C.POINTER(Desc), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     ("fpssft_schedule_generate", C.c_int32, [C.POINTER(Desc), C.c_int32, C.POINTER(C.c_int32)]),
     ("fpssft_plan_create", C.c_int32, [C.POINTER(Desc), C.c_int32, C.POINTER(Tuning), C.POINTER(C.c_void_p)]),
+    ("fpssft_plan", C.c_int32, [C.POINTER(Desc), C.c_int32, C.POINTER(C.c_void_p)]),
     ("fpssft_plan_destroy", C.c_int32, [C.c_void_p]),
     ("fpssft_plan_get_schedule", C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(C.c_int32)]),
     ("fpssft_plan_cube_info", C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(C.c_int32),

@@ -7,14 +7,16 @@
 //                   spectra (precomputed by k_lines for the first chunk,
 //                   gathered and transformed after it: one wave per line in
 //                   registers, a block FFT in LDS, or line by line for long
-//                   lines), the peel of the recovered list
-//                   (construction-subtraction, Sec. 2.2, on the spectra, or
-//                   in time on request), the 1-sparsity test, the phase
-//                   decode and the amplitude (Eq. decoding), the ordered
-//                   append, and the stopping rule.
+//                   lines), the subtraction of the recovered set
+//                   (construction-subtraction, Sec. 2.2: on the spectra,
+//                   through per-bin lists summed exactly, or in time on
+//                   request), the 1-sparsity test, the phase decode and the
+//                   amplitude (Eq. decoding), the merge of a frequency
+//                   detected again, the ordered record, and the stopping
+//                   rule.
 //  k_solve_batched  the same per cube, persistent: work-groups take cube
 //                   indices from a device queue until it is empty.
-//  k_backward       adjoint of the amplitudes with the decisions fixed.
+//  k_backward       adjoint of the set amplitudes with the decisions fixed.
 //  k_reset, k_zero  counter reset and zero fill (kernels, so that they can
 //                   sit inside a captured graph).
 //
@@ -180,57 +182,135 @@ __global__ void k_lines(const CubeDesc* __restrict__ descs, const LineItem* __re
 // ---------------------------------------------------------------------------
 // One cube, one work-group.
 // ---------------------------------------------------------------------------
-struct SolveLds {
-  float2* bufA;    // [(D+1) L] the line spectra, row i = line i
-  float2* bufB;    // the block FFT's second buffer (block path)
-  float2* P;       // [(D+1) L] peel accumulator (wave path; block path with
-                   // the time-domain construction-subtraction)
-  float2* tw;      // [L] twiddles W_L^k
-  float2* rec_a;   // [rec_lds] amplitudes
-  int32_t* rec_f;  // [rec_lds][D] frequency indices
-  int32_t* rec_p;  // [rec_lds] canonical position in the outputs
-  int32_t* rec_t;  // [rec_lds] iteration
-  int32_t* rec_m;  // [rec_lds] bin
-  int* wsum;       // [2][16] per-wave exchange words, double-buffered
-  int* cnt;        // [1] length of the LDS record list
+
+// Record store of one cube. The recovered set holds one slot per distinct
+// frequency, in the order the work-group's waves appended them; the
+// detection trace is in canonical (iteration, bin) order. The store lives in
+// LDS (kRecLds) or in the plan's device workspace, `cap` entries per array.
+struct RecStore {
+  float2* sa;   // [cap] amplitude of a set entry: the sum of its detections
+  int32_t* sf;  // [cap][D] its frequency indices
+  int32_t* sp;  // [cap] its canonical set index; the sign bit marks a
+                // frequency detected more than once
+  int32_t* nx;  // [cap] next entry projecting onto the same bin in this
+                // iteration (-1 ends a list); at the end of the cube, the
+                // slot, then the output position, of each canonical index
+  int32_t* dt;  // [cap] detection: iteration
+  int32_t* dm;  // [cap] detection: bin
+  int32_t* ds;  // [cap] detection: canonical set index of its frequency
 };
 
-// Both layouts take 2 (D+1) L + L values before the records: the wave path
-// the D+1 spectra (each wave's transform writes its row) and the peel
-// accumulator, the block path two line buffers; then the twiddles.
+template <int D>
+__device__ __forceinline__ RecStore carve_records(char* base, int cap) {
+  RecStore r;
+  r.sa = (float2*)base;
+  r.sf = (int32_t*)(r.sa + cap);
+  r.sp = r.sf + cap * D;
+  r.nx = r.sp + cap;
+  r.dt = r.nx + cap;
+  r.dm = r.dt + cap;
+  r.ds = r.dm + cap;
+  return r;
+}
+
+// Record-store accessors: LDS, or device memory through address-space-1
+// instructions.
+template <bool kLds>
+__device__ __forceinline__ int32_t rs_ld(const int32_t* p, int i) {
+  if constexpr (kLds) return p[i];
+  else return ld_gi(p, i);
+}
+template <bool kLds>
+__device__ __forceinline__ void rs_st(int32_t* p, int i, int32_t v) {
+  if constexpr (kLds) p[i] = v;
+  else st_gi(p, i, v);
+}
+template <bool kLds>
+__device__ __forceinline__ float2 rs_ld(const float2* p, int i) {
+  if constexpr (kLds) return p[i];
+  else return ld_g(p, i);
+}
+template <bool kLds>
+__device__ __forceinline__ void rs_st(float2* p, int i, float2 v) {
+  if constexpr (kLds) p[i] = v;
+  else st_g(p, i, v);
+}
+
+// Barrier after record-store writes that other threads read next: LDS only,
+// or every memory access when the store is in device memory.
+template <bool kLds>
+__device__ __forceinline__ void rec_barrier() {
+  if constexpr (kLds) lds_barrier();
+  else __syncthreads();
+}
+
+struct SolveLds {
+  float2* bufA;  // [(D+1) L] the line spectra, row i = line i
+  float2* bufB;  // block path: the FFT's second buffer [(D+1) L]; long
+                 // lines: one line of scratch [L]
+  float2* P;     // [(D+1) L] constructed spectra (time-domain
+                 // construction-subtraction only)
+  float2* tw;    // [L] twiddles W_L^k (long lines: none, read from memory)
+  int* head;     // [L] first set entry of each bin's list (long lines: in
+                 // the scratch line, once the transforms are done)
+  RecStore rec;  // the record store when it is in LDS
+  int* wsum;     // [2][16] per-wave exchange words, double-buffered
+  int* cnt;      // [4]: slots appended; largest amplitude component (float
+                 // bits); set size after a pass that filled the store
+};
+
+// Layout (the host's solve_lds_bytes mirrors it): the wave path keeps the
+// D+1 spectra (each wave's transform writes its row), the block path two
+// line buffers; then the twiddles, the constructed spectra of the
+// time-domain construction-subtraction, the bin-list heads, the records and
+// the exchange words.
 template <int D, bool kWave>
-__device__ __forceinline__ SolveLds carve_solve_lds(char* smem, int L, int rec_lds, bool serial, bool literal) {
+__device__ __forceinline__ SolveLds carve_solve_lds(char* smem, int L, int rec_cap, bool serial, bool literal) {
   SolveLds s;
   s.bufA = (float2*)smem;
+  s.P = nullptr;
+  float2* end;
   if (!kWave && serial) {
-    // long lines: the spectra, one line of scratch, no twiddles (global)
     s.bufB = s.bufA + (D + 1) * L;
-    s.P = nullptr;
-    s.tw = s.bufB + L;
-  } else if constexpr (kWave) {
-    s.bufB = nullptr;
-    s.P = s.bufA + (D + 1) * L;
-    s.tw = s.P + (D + 1) * L;
+    s.tw = nullptr;
+    s.head = (int*)s.bufB;
+    end = s.bufB + L;
   } else {
-    s.bufB = s.bufA + (D + 1) * L;
-    s.P = nullptr;
-    s.tw = s.bufB + (D + 1) * L;
+    if constexpr (kWave) {
+      s.bufB = nullptr;
+      s.tw = s.bufA + (D + 1) * L;
+    } else {
+      s.bufB = s.bufA + (D + 1) * L;
+      s.tw = s.bufB + (D + 1) * L;
+    }
+    end = s.tw + L;
+    if (!kWave && literal) {
+      s.P = end;
+      end += (D + 1) * L;
+    }
+    s.head = (int*)end;
+    end = (float2*)(s.head + ((L + 1) & ~1));
   }
-  float2* end = s.tw + (!kWave && serial ? 0 : L);
-  if (!kWave && !serial && literal) {
-    // block path, time-domain construction-subtraction: constructed spectra
-    s.P = end;
-    end += (D + 1) * L;
-  }
-  s.rec_a = end;
-  s.rec_f = (int32_t*)(s.rec_a + rec_lds);
-  s.rec_p = s.rec_f + rec_lds * D;
-  s.rec_t = s.rec_p + rec_lds;
-  s.rec_m = s.rec_t + rec_lds;
-  s.wsum = s.rec_m + rec_lds;
+  s.rec = carve_records<D>((char*)end, rec_cap);
+  s.wsum = (int*)((char*)end + (size_t)rec_cap * FPS_REC_SLOT_BYTES(D));
   s.cnt = s.wsum + 32;
   return s;
 }
+
+// Exact, order-independent sums of the records' projections: each term is
+// converted to a 64-bit integer at scale 2^e (exact but for its bits below
+// 2^-e), the integers are added, and the sum is converted back once, so the
+// result does not depend on the order of the list. The scale is fixed per
+// iteration from the set size n and a bound on the amplitude components
+// (amax < 2^ea): a term is below sqrt(2) amax, a sum of at most n terms
+// below 2^(en + ea + 1) with n < 2^en, i.e. below 2^62 after scaling.
+__device__ __forceinline__ int fixed_exponent(int n, uint32_t amax_bits) {
+  const int en = 32 - __clz(n > 1 ? n : 1);
+  const int ea = (int)((amax_bits >> 23) & 0xffu) - 126;
+  return 61 - en - ea;
+}
+__device__ __forceinline__ long long to_fixed(float v, int e) { return (long long)__builtin_ldexp((double)v, e); }
+__device__ __forceinline__ float from_fixed(long long v, int e) { return (float)__builtin_ldexp((double)v, -e); }
 
 // Wave path of the solve loop (L = 64 E, 64 <= L <= 512, one wave per
 // line): wave w holds line w's values at l = lane + 64 e in registers.
@@ -281,40 +361,73 @@ __device__ __forceinline__ void wave_fft_to_lds(const float2 (&in)[kEMax], const
   wave_fft_lanes<E>(v, tw, [&](int k, float2 val) { dst[k] = val; });
 }
 
-// Peel (construction-subtraction, Sec. 2.2): the projection of record j
-// onto bin b = [sum_k alpha_k c_k m_k]_L of line i is a_j e^{+j 2 pi p_i / L}
-// with p_i = [sum_k tau_k^{(i)} c_k m_k]_L (Eq. freqSum, Eq. orthogonality).
-// Records j = j0, j0 + js, ... < kc are accumulated into acc (lines astr
-// apart) with the given sign (LDS atomics: several records can share a bin).
+// Construction-subtraction (Sec. 2.2): the recovered sinusoid (m_j, a_j)
+// contributes a_j e^{+j 2 pi p_j^{(i)} / L} to bin b_j = [sum_k alpha_k c_k
+// m_jk]_L of line i, p_j^{(i)} = [sum_k tau_k^{(i)} c_k m_jk]_L (Eq.
+// freqSum, Eq. orthogonality). First, each set entry j = j0, j0 + js, ...
+// < n is linked into the list of its bin for this iteration's slope.
 template <int D, bool kPow2, bool kRecLds>
-__device__ __forceinline__ void peel_records(const Geo<D>& g, const uint32_t (&al)[D], const uint32_t (&ta)[D],
-                                             const SolveLds& s, const OutPtrs& out, const float2* tw, int j0,
-                                             int js, int kc, float2* acc, int astr, float sign) {
+__device__ __forceinline__ void link_bins(const Geo<D>& g, const uint32_t (&al)[D], const RecStore& rs, int* head,
+                                          int j0, int js, int n) {
   const uint32_t L = g.L;
-  const float2* oamps = (const float2*)out.amps;
-  for (int j = j0; j < kc; j += js) {
+  for (int j = j0; j < n; j += js) {
+    uint32_t b = 0;
+#pragma unroll
+    for (int k = 0; k < D; ++k)
+      b = umod<kPow2>(b + al[k] * (g.c[k] * (uint32_t)rs_ld<kRecLds>(rs.sf, j * D + k)), L);
+    rs_st<kRecLds>(rs.nx, j, atomicExch(&head[b], j));
+  }
+}
+
+// Then the thread that owns a bin sums its list's contributions on the D+1
+// lines (fixed point at scale 2^e, so the sum is the same for any list
+// order) into sum[i]. A list holds at most the n set entries, all with
+// slots below n; the walk stops there whatever the links say.
+template <int D, bool kPow2, bool kRecLds>
+__device__ __forceinline__ void list_sum(const Geo<D>& g, const uint32_t (&ta)[D], const RecStore& rs,
+                                         const float2* tw, int h, int n, int e, float2 (&sum)[D + 1]) {
+  const uint32_t L = g.L;
+  long long sr[D + 1], si[D + 1];
+#pragma unroll
+  for (int i = 0; i <= D; ++i) sr[i] = si[i] = 0;
+  for (int j = h, steps = 0; (unsigned)j < (unsigned)n && steps < n; ++steps) {
+    const int nxt = rs_ld<kRecLds>(rs.nx, j);
     uint32_t gk[D];
-    uint32_t b = 0, p0 = 0;
+    uint32_t p0 = 0;
 #pragma unroll
     for (int k = 0; k < D; ++k) {
-      const int32_t f = kRecLds ? s.rec_f[j * D + k] : ld_gi(out.freqs, j * D + k);
-      gk[k] = g.c[k] * (uint32_t)f;
-      b = umod<kPow2>(b + al[k] * gk[k], L);
+      gk[k] = g.c[k] * (uint32_t)rs_ld<kRecLds>(rs.sf, j * D + k);
       p0 = umod<kPow2>(p0 + ta[k] * gk[k], L);
     }
-    const float2 a = kRecLds ? s.rec_a[j] : ld_g(oamps, j);
+    const float2 a = rs_ld<kRecLds>(rs.sa, j);
     float2 c = c_mulc(a, tw[p0]);
-    atomicAdd(&acc[b].x, sign * c.x);
-    atomicAdd(&acc[b].y, sign * c.y);
+    sr[0] += to_fixed(c.x, e);
+    si[0] += to_fixed(c.y, e);
 #pragma unroll
     for (int k = 0; k < D; ++k) {
       uint32_t p = p0 + gk[k];
       if (p >= L) p -= L;
       c = c_mulc(a, tw[p]);
-      atomicAdd(&acc[(k + 1) * astr + b].x, sign * c.x);
-      atomicAdd(&acc[(k + 1) * astr + b].y, sign * c.y);
+      sr[k + 1] += to_fixed(c.x, e);
+      si[k + 1] += to_fixed(c.y, e);
     }
+    j = nxt;
   }
+#pragma unroll
+  for (int i = 0; i <= D; ++i) sum[i] = make_float2(from_fixed(sr[i], e), from_fixed(si[i], e));
+}
+
+// The set entry with frequency f in the list starting at h, or -1. A
+// frequency is in at most one list per iteration (the bin it projects onto).
+template <int D, bool kRecLds>
+__device__ __forceinline__ int find_in_list(const RecStore& rs, int h, int n, const int (&f)[D]) {
+  for (int j = h, steps = 0; (unsigned)j < (unsigned)n && steps < n; j = rs_ld<kRecLds>(rs.nx, j), ++steps) {
+    bool eq = true;
+#pragma unroll
+    for (int k = 0; k < D; ++k) eq = eq && rs_ld<kRecLds>(rs.sf, j * D + k) == f[k];
+    if (eq) return j;
+  }
+  return -1;
 }
 
 // Bin m of one iteration (r: its value on lines 0..D after the peel): the
@@ -378,21 +491,27 @@ __device__ __forceinline__ bool decode_bin(const Geo<D>& g, const uint32_t (&al)
   return cand;
 }
 
-// kRecLds: the record list lives in LDS (in the order the work-group's waves
-// appended it, which the peel does not depend on) and is written to the
-// outputs in canonical order; otherwise the peel reads the outputs.
+// One cube in one work-group, iteration by iteration (Sec. 2.2).
 //
 // One iteration (wave path, more waves than lines): waves 0..D transform
-// their line into bufA while the remaining waves peel the records found so
-// far into P; one barrier; every bin is tested and decoded from bufA - P
-// (and P cleared for the iteration after next); one barrier per pass of
-// bins exchanges the per-wave candidate counts and nonzero flags. Other
-// configurations peel straight into the spectra after the transform, with a
-// barrier on each side.
+// their line into bufA while the remaining waves link the set entries into
+// per-bin lists; one barrier; the owner of each bin subtracts its list's
+// contributions from the spectra (construction-subtraction) and tests and
+// decodes the bin (Eq. decoding); one barrier per pass of bins exchanges
+// the per-wave counts of detections and new frequencies and the nonzero
+// flags. Other configurations link the entries after the transform, with
+// a barrier on each side.
+//
+// A detection whose frequency is already in the set (found in that bin's
+// list) adds its amplitude to that entry; otherwise it opens a new entry.
+// The lists give each bin exactly the entries that project onto it, so the
+// subtraction is the same as summing every detection (the set amplitudes
+// are sums of detections).
 template <int D, bool kPow2, bool kRecLds, bool kWave>
 __device__ __forceinline__ void solve_cube(const CubeDesc& cd, const float2* __restrict__ x, const OutPtrs out,
                                            const int32_t* __restrict__ sched, const float2* __restrict__ twall,
-                                           const float2* __restrict__ pre, int pre_count, char* smem) {
+                                           const float2* __restrict__ pre, int pre_count, char* smem,
+                                           char* recws) {
   const Geo<D> g = load_geo<D>(cd);
   const uint32_t L = g.L;
   const int T = cd.T;
@@ -412,8 +531,13 @@ __device__ __forceinline__ void solve_cube(const CubeDesc& cd, const float2* __r
   const bool literal = !(kWave && kPow2) && !serial && (cd.flags & FPS_LITERAL_PEEL) != 0;
   const bool avg = (cd.flags & FPS_AMP_AVERAGE) != 0;
   SolveLds s = carve_solve_lds<D, kWave>(smem, (int)L, kRecLds ? cd.rec_lds : 0, serial, literal);
-  if (!serial)
-    for (uint32_t e = tid; e < L; e += B) s.tw[e] = ld_g(twall, cd.tw_off + e);
+  const RecStore rs = kRecLds ? s.rec : carve_records<D>(recws + cd.rec_off, max_k);
+  if (!serial) {
+    for (uint32_t e = tid; e < L; e += B) {
+      s.tw[e] = ld_g(twall, cd.tw_off + e);
+      s.head[e] = -1;
+    }
+  }
   const float2* tw = serial ? twall + cd.tw_off : s.tw;
   float2* oamps = (float2*)out.amps;
   const bool use_pf = !serial && L <= (uint32_t)(kPfU * B);
@@ -424,11 +548,10 @@ __device__ __forceinline__ void solve_cube(const CubeDesc& cd, const float2* __r
   // The host sends a cube here only if 64 <= L <= 512 and blockDim has at
   // least D+1 waves.
   constexpr bool wave_path = kWave && kPow2;
-  // Peel concurrently with the transforms when some waves have no line.
-  const bool conc = kRecLds && wave_path && nw > D + 1;
-  if (tid == 0) s.cnt[0] = 0;
-  if constexpr (wave_path)
-    for (uint32_t e = tid; e < (D + 1) * L; e += B) s.P[e] = make_float2(0.f, 0.f);
+  // Link the entries concurrently with the transforms when some waves have
+  // no line.
+  const bool conc = wave_path && nw > D + 1;
+  if (tid < 4) s.cnt[tid] = 0;
 
   Prefetch<D> pf;
   float2 pfw[kEMax];
@@ -440,10 +563,13 @@ __device__ __forceinline__ void solve_cube(const CubeDesc& cd, const float2* __r
     prefetch_issue<D, kPow2>(pf, g, x, sch, pre, 0 < pre_count);
   }
 
-  int kc = 0;
+  int kc_det = 0;   // detections recorded (the capacity counts these)
+  int kc_set = 0;   // distinct frequencies recorded
+  bool any_merge = false;
   int xpar = 0;
   int status = kStatusIncomplete;
   int iters = T;
+  bool full = false;
   for (int t = 0; t < T; ++t) {
     const int32_t* at = sch + t * 2 * D;
     const bool precomputed = t < pre_count;
@@ -453,7 +579,7 @@ __device__ __forceinline__ void solve_cube(const CubeDesc& cd, const float2* __r
       al[k] = (uint32_t)at[k];
       ta[k] = (uint32_t)at[D + k];
     }
-    float2* S;
+    const float2* S;
     if constexpr (wave_path) {
       if (wv <= D) {
         // Consume the prefetched samples first, so that the registers they
@@ -482,15 +608,14 @@ __device__ __forceinline__ void solve_cube(const CubeDesc& cd, const float2* __r
         }
         // The next iteration's gathers are issued after the transform: in
         // flight, scattered loads slow this wave's LDS traffic several-fold;
-        // they overlap the peel and the decode instead.
+        // they overlap the list links and the decode instead.
         if (t + 1 < T)
           wave_prefetch<D, kPow2>(pfw, E, g, x, at + 2 * D, pre + (int64_t)(t + 1) * (D + 1) * L, t + 1 < pre_count,
                                   wv);
       } else if (conc) {
-        const int pt = tid - (D + 1) * 64;
-        peel_records<D, kPow2, kRecLds>(g, al, ta, s, out, tw, pt, B - (D + 1) * 64, kc, s.P, (int)L, 1.0f);
+        link_bins<D, kPow2, kRecLds>(g, al, rs, s.head, tid - (D + 1) * 64, B - (D + 1) * 64, kc_set);
       }
-      lds_barrier();
+      rec_barrier<kRecLds>();
       S = s.bufA;
     } else if (serial) {
       for (int line = 0; line <= D; ++line) {
@@ -519,9 +644,18 @@ __device__ __forceinline__ void solve_cube(const CubeDesc& cd, const float2* __r
         // spectra (Eq. freqSum) go through an unnormalised inverse DFT, read
         // as the forward DFT at index (L - l) mod L, and are subtracted from
         // the samples (held divided by L, hence the constructed ones too).
-        for (uint32_t e = tid; e < (D + 1) * L; e += B) s.P[e] = make_float2(0.f, 0.f);
-        lds_barrier();
-        peel_records<D, kPow2, kRecLds>(g, al, ta, s, out, tw, tid, B, kc, s.P, (int)L, 1.0f);
+        link_bins<D, kPow2, kRecLds>(g, al, rs, s.head, tid, B, kc_set);
+        rec_barrier<kRecLds>();
+        const int fe = fixed_exponent(kc_set, (uint32_t)s.cnt[1]);
+        for (uint32_t m = tid; m < L; m += B) {
+          float2 sum[D + 1];
+#pragma unroll
+          for (int i = 0; i <= D; ++i) sum[i] = make_float2(0.f, 0.f);
+          const int h = s.head[m];
+          if (h >= 0) list_sum<D, kPow2, kRecLds>(g, ta, rs, tw, h, kc_set, fe, sum);
+#pragma unroll
+          for (int i = 0; i <= D; ++i) s.P[i * L + m] = sum[i];
+        }
         lds_barrier();
         const float2* R = block_fft<kPow2>(s.P, s.bufB, D + 1, (int)L, cd.nstages, cd.radix, tw);
         for (int i = 0; i <= D; ++i)
@@ -536,118 +670,173 @@ __device__ __forceinline__ void solve_cube(const CubeDesc& cd, const float2* __r
         prefetch_issue<D, kPow2>(pf, g, x, at + 2 * D, pre + (int64_t)(t + 1) * (D + 1) * L, t + 1 < pre_count);
     }
     if (!conc && !literal) {
-      peel_records<D, kPow2, kRecLds>(g, al, ta, s, out, tw, tid, B, kc, S, (int)L, -1.0f);
-      lds_barrier();
+      if (serial) {
+        // the heads live in the scratch line, free once the lines are done
+        for (uint32_t e = tid; e < L; e += B) s.head[e] = -1;
+        lds_barrier();
+      }
+      link_bins<D, kPow2, kRecLds>(g, al, rs, s.head, tid, B, kc_set);
+      rec_barrier<kRecLds>();
     }
+    // scale of this iteration's exact list sums
+    const int fe = fixed_exponent(kc_set, (uint32_t)s.cnt[1]);
 
-    // Test, decode and append, bins in ascending order: a pass covers up to
+    // Test, decode and record, bins in ascending order: a pass covers up to
     // kDecodeBins bins per thread (bin m0 + j B + tid for the j-th), with one
     // exchange barrier for all of them.
     bool nonzero = false;
-    bool full = false;
     bool any = false;
     constexpr int kNB = D >= 4 ? 1 : kDecodeBins;  // 4-D: register budget
     const int nbp = min(kNB, (int)((L + (uint32_t)B - 1) / (uint32_t)B));
     for (uint32_t m0 = 0; m0 < L; m0 += (uint32_t)(B * nbp)) {
-      bool cand[kNB];
+      bool cand[kNB], isnew[kNB];
       int f[kNB][D];
       float2 amp[kNB];
-      int slot[kNB], before[kNB], wcnt[kNB];
+      int mslot[kNB], slot[kNB], bdet[kNB], bnew[kNB], wdet[kNB], wnew[kNB];
       int wall = 0;
+      const unsigned long long lt = (1ull << lane) - 1ull;
 #pragma unroll
       for (int j = 0; j < kNB; ++j) {
         const uint32_t m = m0 + (uint32_t)(j * B) + tid;
         cand[j] = false;
+        isnew[j] = false;
         amp[j] = make_float2(0.f, 0.f);
+        mslot[j] = -1;
         slot[j] = -1;
         if (j < nbp && m < L) {
           float2 r[D + 1];
 #pragma unroll
           for (int i = 0; i <= D; ++i) r[i] = S[i * L + m];
-          if (conc) {
+          const int h = s.head[m];
+          if (h >= 0 && !literal) {
+            float2 sum[D + 1];
+            list_sum<D, kPow2, kRecLds>(g, ta, rs, tw, h, kc_set, fe, sum);
 #pragma unroll
-            for (int i = 0; i <= D; ++i) {
-              r[i] = c_sub(r[i], s.P[i * L + m]);
-              s.P[i * L + m] = make_float2(0.f, 0.f);
-            }
+            for (int i = 0; i <= D; ++i) r[i] = c_sub(r[i], sum[i]);
           }
           cand[j] = decode_bin<D, kPow2>(g, al, ta, r, m, th0, rho, gtol, tw, avg, nonzero, f[j], amp[j]);
+          if (h >= 0) {
+            if (cand[j]) mslot[j] = find_in_list<D, kRecLds>(rs, h, kc_set, f[j]);
+            s.head[m] = -1;  // the list is rebuilt next iteration
+          }
+          isnew[j] = cand[j] && mslot[j] < 0;
         }
-        const unsigned long long bal = __ballot(cand[j] ? 1 : 0);
-        wcnt[j] = __popcll(bal);
-        before[j] = __popcll(bal & ((1ull << lane) - 1ull));
-        wall += wcnt[j];
+        const unsigned long long bd = __ballot(cand[j] ? 1 : 0);
+        const unsigned long long bn = __ballot(isnew[j] ? 1 : 0);
+        wdet[j] = __popcll(bd);
+        bdet[j] = __popcll(bd & lt);
+        wnew[j] = __popcll(bn);
+        bnew[j] = __popcll(bn & lt);
+        wall += wnew[j];
       }
-      if (kRecLds && wall > 0) {
-        // Append to the LDS list now (one atomic per wave), so that the next
-        // iteration's peel needs no barrier after the exchange below.
+      if (wall > 0) {
+        // New frequencies go to the store now (one atomic per wave), so that
+        // the next iteration can link them with no barrier after the
+        // exchange below.
         int base = 0;
-        if (lane == 0) base = atomicAdd(s.cnt, wall);
+        if (lane == 0) base = atomicAdd(&s.cnt[0], wall);
         base = __builtin_amdgcn_readlane(base, 0);
 #pragma unroll
         for (int j = 0; j < kNB; ++j) {
-          slot[j] = base + before[j];
-          base += wcnt[j];
-          if (cand[j] && slot[j] < cd.rec_lds) {
+          slot[j] = base + bnew[j];
+          base += wnew[j];
+          if (isnew[j] && slot[j] < max_k) {
 #pragma unroll
-            for (int k = 0; k < D; ++k) s.rec_f[slot[j] * D + k] = f[j][k];
-            s.rec_a[slot[j]] = amp[j];
-            s.rec_t[slot[j]] = t;
-            s.rec_m[slot[j]] = (int32_t)(m0 + (uint32_t)(j * B) + tid);
+            for (int k = 0; k < D; ++k) rs_st<kRecLds>(rs.sf, slot[j] * D + k, f[j][k]);
+            rs_st<kRecLds>(rs.sa, slot[j], amp[j]);
           }
         }
       }
-      // exchange word: 8 bits of candidate count per bin set, nonzero flag
+      // exchange word: 7 bits each of the detection and new-frequency counts
+      // per bin set, the nonzero flag in bit 28
       const bool wnz = __ballot(nonzero ? 1 : 0) != 0ull;
-      int wword = wnz ? (1 << 24) : 0;
+      int wword = wnz ? (1 << 28) : 0;
 #pragma unroll
-      for (int j = 0; j < kNB; ++j) wword |= wcnt[j] << (8 * j);
+      for (int j = 0; j < kNB; ++j) wword |= (wdet[j] | (wnew[j] << 7)) << (14 * j);
       if (lane == 0) s.wsum[xpar * 16 + wv] = wword;
       lds_barrier();
       // one LDS read per lane, then the words are taken from the lanes
       const int word = lane < nw ? s.wsum[xpar * 16 + lane] : 0;
-      int pre[kNB], tot[kNB];
+      int pdet[kNB], tdet[kNB], pnew[kNB], tnew[kNB];
 #pragma unroll
-      for (int j = 0; j < kNB; ++j) pre[j] = tot[j] = 0;
+      for (int j = 0; j < kNB; ++j) pdet[j] = tdet[j] = pnew[j] = tnew[j] = 0;
       any = false;
       for (int w = 0; w < nw; ++w) {
         const int v = __builtin_amdgcn_readlane(word, w);
 #pragma unroll
         for (int j = 0; j < kNB; ++j) {
-          const int c = (v >> (8 * j)) & 0xff;
-          pre[j] += (w < wv) ? c : 0;
-          tot[j] += c;
+          const int cdn = (v >> (14 * j)) & 0x7f;
+          const int cnn = (v >> (14 * j + 7)) & 0x7f;
+          pdet[j] += (w < wv) ? cdn : 0;
+          pnew[j] += (w < wv) ? cnn : 0;
+          tdet[j] += cdn;
+          tnew[j] += cnn;
         }
-        any |= (v >> 24) != 0;
+        any |= ((v >> 28) & 1) != 0;
       }
       xpar ^= 1;
-      int done = 0;  // candidates of the earlier bin sets of this pass
+      int sum_det = 0, sum_new = 0;
+#pragma unroll
+      for (int j = 0; j < kNB; ++j) {
+        sum_det += tdet[j];
+        sum_new += tnew[j];
+      }
+      // The store is full: the detections up to capacity are kept, in
+      // canonical order, and the run stops.
+      const bool fullp = kc_det + sum_det > max_k;
+      any_merge |= sum_det != sum_new;
+      int done_det = 0, done_new = 0;  // counts of the earlier bin sets
+      // (device-memory store: the wave-order writes of a full pass must land
+      // before the canonical ones below)
+      if constexpr (!kRecLds) {
+        if (fullp) __syncthreads();
+      }
 #pragma unroll
       for (int j = 0; j < kNB; ++j) {
         if (cand[j]) {
-          const int idx = kc + done + pre[j] + before[j];
-          if (kRecLds && slot[j] < cd.rec_lds) {
-            // written out at the end of the cube (global stores issued now
-            // would queue behind the next iteration's gathers)
-            s.rec_p[slot[j]] = idx;
-          } else if (idx < max_k) {
+          const int di = kc_det + done_det + pdet[j] + bdet[j];
+          if (di < max_k) {
+            int si;
+            float2 av;
+            if (isnew[j]) {
+              si = kc_set + done_new + pnew[j] + bnew[j];
+              int sl = slot[j];
+              if (fullp) {
+                // Slots went to this pass's new frequencies in wave order;
+                // the ones kept move to their canonical slots (all of them
+                // hold their values in registers).
+                sl = si;
 #pragma unroll
-            for (int k = 0; k < D; ++k) st_gi(out.freqs, idx * D + k, f[j][k]);
-            st_g(oamps, idx, amp[j]);
-            st_gi(out.rec_iter, idx, t);
-            st_gi(out.rec_bin, idx, (int32_t)(m0 + (uint32_t)(j * B) + tid));
+                for (int k = 0; k < D; ++k) rs_st<kRecLds>(rs.sf, sl * D + k, f[j][k]);
+                rs_st<kRecLds>(rs.sa, sl, amp[j]);
+                atomicMax(&s.cnt[2], si + 1);
+              }
+              if (sl < max_k) rs_st<kRecLds>(rs.sp, sl, si);
+              av = amp[j];
+            } else {
+              // detected again: the amplitude joins the first record
+              si = rs_ld<kRecLds>(rs.sp, mslot[j]) & 0x7fffffff;
+              av = c_add(rs_ld<kRecLds>(rs.sa, mslot[j]), amp[j]);
+              rs_st<kRecLds>(rs.sa, mslot[j], av);
+              rs_st<kRecLds>(rs.sp, mslot[j], (int32_t)((uint32_t)si | 0x80000000u));
+            }
+            rs_st<kRecLds>(rs.dt, di, t);
+            rs_st<kRecLds>(rs.dm, di, (int32_t)(m0 + (uint32_t)(j * B) + tid));
+            rs_st<kRecLds>(rs.ds, di, si);
+            atomicMax((unsigned int*)&s.cnt[1], __float_as_uint(fmaxf(fabsf(av.x), fabsf(av.y))));
           }
         }
-        done += tot[j];
+        done_det += tdet[j];
+        done_new += tnew[j];
       }
-      if (kc + done > max_k) {
+      if (fullp) {
         full = true;
-        kc = max_k;
         break;
       }
-      kc += done;
+      kc_det += done_det;
+      kc_set += done_new;
     }
-    // Records kept in global memory are read by other threads next
+    // Records kept in device memory are read by other threads next
     // iteration: make the stores visible across the work-group.
     if (!kRecLds) __syncthreads();
     if (full) {
@@ -661,27 +850,87 @@ __device__ __forceinline__ void solve_cube(const CubeDesc& cd, const float2* __r
       break;
     }
   }
-  if constexpr (kRecLds) {
-    // The LDS record list, in the order the waves appended it, goes to its
-    // canonical positions (entries past the capacity are dropped).
-    lds_barrier();
-    const int n = min(s.cnt[0], cd.rec_lds);
-    for (int j = tid; j < n; j += B) {
-      const int idx = s.rec_p[j];
-      if (idx < max_k) {
+
+  // End of the cube: the set and the detections go to the outputs. Without
+  // a re-detection the set is in first-detection order at the canonical
+  // indices; otherwise a merged frequency whose amplitude sum has |a| <=
+  // theta0 is not part of the set (Eq. sigModel2: a != 0) and moves behind
+  // the kept ones, both groups in first-detection order.
+  rec_barrier<kRecLds>();
+  if (full) {
+    kc_det = max_k;
+    kc_set = max(kc_set, s.cnt[2]);
+  }
+  const int nset = kc_set;
+  int kept = nset;
+  if (!any_merge) {
+    for (int j = tid; j < nset; j += B) {
+      const int pos = rs_ld<kRecLds>(rs.sp, j);
 #pragma unroll
-        for (int k = 0; k < D; ++k) st_gi(out.freqs, idx * D + k, s.rec_f[j * D + k]);
-        st_g(oamps, idx, s.rec_a[j]);
-        st_gi(out.rec_iter, idx, s.rec_t[j]);
-        st_gi(out.rec_bin, idx, s.rec_m[j]);
-      }
+      for (int k = 0; k < D; ++k) st_gi(out.freqs, pos * D + k, rs_ld<kRecLds>(rs.sf, j * D + k));
+      st_g(oamps, pos, rs_ld<kRecLds>(rs.sa, j));
     }
+  } else {
+    for (int j = tid; j < nset; j += B) rs_st<kRecLds>(rs.nx, rs_ld<kRecLds>(rs.sp, j) & 0x7fffffff, j);
+    rec_barrier<kRecLds>();
+    const unsigned long long lt = (1ull << lane) - 1ull;
+    int ck = 0, cdrop = 0;
+    for (int base = 0; base < nset; base += B) {
+      const int pos = base + tid;
+      int j = -1;
+      bool drop = false, keep = false;
+      if (pos < nset) {
+        j = rs_ld<kRecLds>(rs.nx, pos);
+        const float2 a = rs_ld<kRecLds>(rs.sa, j);
+        drop = rs_ld<kRecLds>(rs.sp, j) < 0 && sqrtf(a.x * a.x + a.y * a.y) <= th0;
+        keep = !drop;
+      }
+      const unsigned long long bd = __ballot(drop ? 1 : 0);
+      const unsigned long long bk = __ballot(keep ? 1 : 0);
+      if (lane == 0) s.wsum[xpar * 16 + wv] = __popcll(bd) | (__popcll(bk) << 8);
+      lds_barrier();
+      const int word = lane < nw ? s.wsum[xpar * 16 + lane] : 0;
+      int pd = 0, pk = 0, td = 0, tk = 0;
+      for (int w = 0; w < nw; ++w) {
+        const int v = __builtin_amdgcn_readlane(word, w);
+        pd += (w < wv) ? (v & 0xff) : 0;
+        pk += (w < wv) ? ((v >> 8) & 0xff) : 0;
+        td += v & 0xff;
+        tk += (v >> 8) & 0xff;
+      }
+      xpar ^= 1;
+      // rank among the kept (>= 0) or among the dropped (~rank < 0)
+      if (pos < nset)
+        rs_st<kRecLds>(rs.sp, j, drop ? ~(cdrop + pd + __popcll(bd & lt)) : ck + pk + __popcll(bk & lt));
+      cdrop += td;
+      ck += tk;
+    }
+    rec_barrier<kRecLds>();
+    kept = ck;
+    for (int pos = tid; pos < nset; pos += B) {
+      const int j = rs_ld<kRecLds>(rs.nx, pos);
+      const int enc = rs_ld<kRecLds>(rs.sp, j);
+      const int fin = enc >= 0 ? enc : kept + ~enc;
+#pragma unroll
+      for (int k = 0; k < D; ++k) st_gi(out.freqs, fin * D + k, rs_ld<kRecLds>(rs.sf, j * D + k));
+      st_g(oamps, fin, rs_ld<kRecLds>(rs.sa, j));
+      rs_st<kRecLds>(rs.nx, pos, fin);
+    }
+    rec_barrier<kRecLds>();
+  }
+  for (int i = tid; i < kc_det; i += B) {
+    st_gi(out.rec_iter, i, rs_ld<kRecLds>(rs.dt, i));
+    st_gi(out.rec_bin, i, rs_ld<kRecLds>(rs.dm, i));
+    const int si = rs_ld<kRecLds>(rs.ds, i);
+    st_gi(out.rec_sin, i, any_merge ? rs_ld<kRecLds>(rs.nx, si) : si);
   }
   if (tid == 0) {
-    st_gi(out.info, 0, kc);
+    st_gi(out.info, 0, kept);
     st_gi(out.info, 1, iters);
     st_gi(out.info, 2, status);
-    st_gi(out.info, 3, 0);
+    st_gi(out.info, 3, kc_det);
+    st_gi(out.info, 4, nset - kept);
+    for (int q = 5; q < FPS_INFO_LEN; ++q) st_gi(out.info, q, 0);
   }
   __syncthreads();
 }
@@ -692,10 +941,11 @@ __device__ __forceinline__ void solve_cube(const CubeDesc& cd, const float2* __r
 
 template <int D, bool kPow2, bool kRecLds, bool kWave>
 __global__ FPS_SOLVE_ATTRS void k_solve_plain(const CubeDesc* __restrict__ descs, int cube, const float2* __restrict__ x,
-                              OutPtrs out, const int32_t* __restrict__ sched, const float2* __restrict__ tw,
-                              const float2* __restrict__ pre, int pre_count) {
+                                              OutPtrs out, const int32_t* __restrict__ sched,
+                                              const float2* __restrict__ tw, const float2* __restrict__ pre,
+                                              int pre_count, char* recws) {
   extern __shared__ __attribute__((aligned(16))) char lds_solve[];
-  solve_cube<D, kPow2, kRecLds, kWave>(descs[cube], x, out, sched, tw, pre, pre_count, lds_solve);
+  solve_cube<D, kPow2, kRecLds, kWave>(descs[cube], x, out, sched, tw, pre, pre_count, lds_solve, recws);
 }
 
 // Persistent: every work-group loops taking the next cube of `order` from
@@ -706,9 +956,9 @@ __global__ FPS_SOLVE_ATTRS void k_solve_plain(const CubeDesc* __restrict__ descs
 // kernel precedes the launch.
 template <int D, bool kPow2, bool kRecLds, bool kWave>
 __global__ FPS_SOLVE_ATTRS void k_solve_batched(const CubeDesc* __restrict__ descs, const float2* const* __restrict__ xs,
-                                const OutPtrs* __restrict__ outs, const int32_t* __restrict__ sched,
-                                const float2* __restrict__ tw, const int32_t* __restrict__ order, int ncubes,
-                                int* __restrict__ queue) {
+                                                const OutPtrs* __restrict__ outs, const int32_t* __restrict__ sched,
+                                                const float2* __restrict__ tw, const int32_t* __restrict__ order,
+                                                int ncubes, int* __restrict__ queue, char* recws) {
   extern __shared__ __attribute__((aligned(16))) char lds_solve[];
   __shared__ int s_idx;
   for (;;) {
@@ -725,7 +975,7 @@ __global__ FPS_SOLVE_ATTRS void k_solve_batched(const CubeDesc* __restrict__ des
       break;
     }
     const int c = __builtin_amdgcn_readfirstlane(order[idx]);
-    solve_cube<D, kPow2, kRecLds, kWave>(descs[c], xs[c], outs[c], sched, tw, nullptr, 0, lds_solve);
+    solve_cube<D, kPow2, kRecLds, kWave>(descs[c], xs[c], outs[c], sched, tw, nullptr, 0, lds_solve, recws);
   }
 }
 
@@ -744,14 +994,16 @@ __global__ void k_zero(float2* const* __restrict__ bufs, const int64_t* __restri
 }
 
 // ---------------------------------------------------------------------------
-// Adjoint of the amplitudes (decisions fixed). Forward, per record i found
-// at iteration t in bin m:  a_i = W^{p_i} (s_hat^{(t,0)}(m) - sum_j a_j
-// W^{-p_j^{(t)}}) over records j of earlier iterations in bin m, with
-// W = exp(-j 2 pi / L), p = [sum_k tau_k^{(t)} c_k m_k]_L. Reverse order:
-// r_bar = W^{-p_i} a_bar_i flows to bin m of line 0 of iteration t and,
-// negated and rotated by W^{p_j^{(t)}}, to the earlier records j in that bin.
-// The line cotangent goes back through the 1/L DFT (an inverse DFT with 1/L)
-// and is added at the line-0 sample positions.
+// Adjoint of the set amplitudes (decisions fixed). Forward, per detection i
+// found at iteration t in bin m:  a_i = W^{p_i} (s_hat^{(t,0)}(m) - sum_j
+// a_j W^{-p_j^{(t)}}) over detections j of earlier iterations in bin m, with
+// W = exp(-j 2 pi / L), p = [sum_k tau_k^{(t)} c_k m_k]_L; a set amplitude is
+// the sum of its detections, so a detection's cotangent starts as its
+// entry's. Reverse order: r_bar =
+// W^{-p_i} a_bar_i flows to bin m of line 0 of iteration t and, negated and
+// rotated by W^{p_j^{(t)}}, to the earlier detections j in that bin. The
+// line cotangent goes back through the 1/L DFT (an inverse DFT with 1/L) and
+// is added at the line-0 sample positions.
 // ---------------------------------------------------------------------------
 template <int D, bool kPow2>
 __device__ __forceinline__ void backward_cube(const CubeDesc& cd, const OutPtrs fwd, const float2* __restrict__ ga,
@@ -764,14 +1016,22 @@ __device__ __forceinline__ void backward_cube(const CubeDesc& cd, const OutPtrs 
   float2* rbar = (float2*)smem;  // [L] line-0 spectrum cotangent
   float2* scratch = rbar + L;    // [L] FFT ping-pong
   float2* tw = scratch + L;      // [L] twiddles
-  float2* abar = tw + L;         // [max_k]
+  float2* abar = tw + L;         // [max_k] detection cotangents
   __shared__ int sh_s, sh_t;
 
   for (uint32_t e = tid; e < L; e += B) tw[e] = ld_g(twall, cd.tw_off + e);
-  const int k = min(ld_gi(fwd.info, 0), cd.max_k);
-  for (int i = tid; i < k; i += B) abar[i] = ld_g(ga, i);
+  // the set and the merged frequencies left out of it: every entry the
+  // forward wrote is a sum of detections
+  const int nent = min(max(ld_gi(fwd.info, 0), 0) + max(ld_gi(fwd.info, 4), 0), cd.max_k);
+  const int n = min(max(ld_gi(fwd.info, 3), 0), cd.max_k);
+  // Entries that no forward run can have written (set index, bin or
+  // iteration out of range) are skipped rather than trusted as indices.
+  for (int i = tid; i < n; i += B) {
+    const int si = ld_gi(fwd.rec_sin, i);
+    abar[i] = (si >= 0 && si < nent) ? ld_g(ga, si) : make_float2(0.f, 0.f);
+  }
   __syncthreads();
-  int e = k;
+  int e = n;
   while (e > 0) {
     if (tid == 0) {
       const int tt = ld_gi(fwd.rec_iter, e - 1);
@@ -784,8 +1044,6 @@ __device__ __forceinline__ void backward_cube(const CubeDesc& cd, const OutPtrs 
     __syncthreads();
     const int s0 = sh_s;
     const int t = sh_t;
-    // Entries that no forward run can have written (bin or iteration out of
-    // range) are skipped rather than trusted as LDS or schedule indices.
     const bool t_ok = t >= 0 && t < cd.T;
     const int32_t* at = sched + cd.sched_off + (t_ok ? t : 0) * 2 * D;
     uint32_t al[D], ta[D];
@@ -794,22 +1052,25 @@ __device__ __forceinline__ void backward_cube(const CubeDesc& cd, const OutPtrs 
       al[q] = (uint32_t)at[q];
       ta[q] = (uint32_t)at[D + q];
     }
-    // Records of iteration t: distinct bins, so plain stores.
+    // Detections of iteration t: distinct bins, so plain stores.
     for (int i = s0 + tid; i < e; i += B) {
       const int m = ld_gi(fwd.rec_bin, i);
-      if (!t_ok || m < 0 || m >= (int)L) continue;
+      const int si = ld_gi(fwd.rec_sin, i);
+      if (!t_ok || m < 0 || m >= (int)L || si < 0 || si >= cd.max_k) continue;
       uint32_t p = 0;
 #pragma unroll
-      for (int q = 0; q < D; ++q) p = umod<kPow2>(p + ta[q] * (g.c[q] * (uint32_t)ld_gi(fwd.freqs, i * D + q)), L);
+      for (int q = 0; q < D; ++q) p = umod<kPow2>(p + ta[q] * (g.c[q] * (uint32_t)ld_gi(fwd.freqs, si * D + q)), L);
       rbar[m] = c_mulc(abar[i], tw[p]);
     }
     __syncthreads();
-    // Earlier records that iteration t's peel subtracted.
+    // Earlier detections that iteration t's construction-subtraction removed.
     for (int j = tid; j < s0; j += B) {
+      const int si = ld_gi(fwd.rec_sin, j);
+      if (si < 0 || si >= cd.max_k) continue;
       uint32_t b = 0, p = 0;
 #pragma unroll
       for (int q = 0; q < D; ++q) {
-        const uint32_t gq = g.c[q] * (uint32_t)ld_gi(fwd.freqs, j * D + q);
+        const uint32_t gq = g.c[q] * (uint32_t)ld_gi(fwd.freqs, si * D + q);
         b = umod<kPow2>(b + al[q] * gq, L);
         p = umod<kPow2>(p + ta[q] * gq, L);
       }
@@ -942,7 +1203,7 @@ hipError_t launch_solve_plain(const LaunchCtx& ctx, const KernelKey& key, int cu
                               hipStream_t st) {
   FPS_DISPATCH_SOLVE(key, {
     hipLaunchKernelGGL((k_solve_plain<kD, kP, kR, kW>), dim3(1), dim3(threads), lds, st, ctx.descs, cube, x, out,
-                       ctx.sched, ctx.tw, pre, pre_count);
+                       ctx.sched, ctx.tw, pre, pre_count, ctx.rec_ws);
   })
   return hipGetLastError();
 }
@@ -957,7 +1218,7 @@ hipError_t launch_solve_batched(const LaunchCtx& ctx, const KernelKey& key, cons
                                 size_t lds, int threads, hipStream_t st) {
   FPS_DISPATCH_SOLVE(key, {
     hipLaunchKernelGGL((k_solve_batched<kD, kP, kR, kW>), dim3(grid), dim3(threads), lds, st, ctx.descs, xs, outs,
-                       ctx.sched, ctx.tw, order, ncubes, queue);
+                       ctx.sched, ctx.tw, order, ncubes, queue, ctx.rec_ws);
   })
   return hipGetLastError();
 }

@@ -12,6 +12,7 @@ struct LaunchCtx {
   const CubeDesc* descs;
   const int32_t* sched;
   const float2* tw;
+  char* rec_ws;  // record stores of the cubes whose records exceed LDS
 };
 
 // Which kernel instantiation serves a cube: dimension count, power-of-two

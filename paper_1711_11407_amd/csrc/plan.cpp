@@ -78,7 +78,8 @@ fpssft_status validate(const fpssft_desc* d, int32_t* L_out, int32_t* T_out) {
   if (!std::isfinite(d->mag_rel_tol) || d->mag_rel_tol < 0.f) return FPSSFT_ERR_INVALID_ARG;
   if (!std::isfinite(d->grid_tol)) return FPSSFT_ERR_INVALID_ARG;
   if (d->schedule && d->max_iters == 0) return FPSSFT_ERR_INVALID_ARG;
-  if (d->flags & ~(FPSSFT_FLAG_AXIS_SCHEDULE | FPSSFT_FLAG_AMP_AVERAGE | FPSSFT_FLAG_LITERAL_PEEL))
+  if (d->flags & ~(FPSSFT_FLAG_AXIS_SCHEDULE | FPSSFT_FLAG_AMP_AVERAGE | FPSSFT_FLAG_LITERAL_PEEL |
+                   FPSSFT_FLAG_DETERMINISTIC))
     return FPSSFT_ERR_INVALID_ARG;
   const int64_t L = lcm_dims(d->dims, d->ndim, kMaxL);
   if (L < 0) return FPSSFT_ERR_UNSUPPORTED;
@@ -239,7 +240,6 @@ struct fpssft_plan_st {
   int ncu = 0;
   size_t lds_max = 0;
   fpssft_tuning tune{};
-  bool rec_lds = true;
   std::vector<CubeDesc> descs;
   std::vector<int32_t> sched;
   std::vector<float2> tw;
@@ -252,6 +252,8 @@ struct fpssft_plan_st {
   float2* d_tw = nullptr;
   // plain path
   float2* d_pre = nullptr;
+  // record stores of the cubes whose records do not fit in LDS
+  char* d_recws = nullptr;
   // batched path
   int32_t* d_order = nullptr;
   int* d_queue = nullptr;
@@ -276,21 +278,35 @@ bool wave_eligible(const CubeDesc& c) {
   return c.Lmask >= 0 && c.L >= 64 && c.L <= 512 && !(c.flags & FPS_LITERAL_PEEL);
 }
 
-size_t solve_lds_bytes(const CubeDesc& c, int rec_lds) {
-  if (c.serial) {
-    // long lines: the D+1 spectra and one line of scratch
-    size_t b = (size_t)(c.D + 2) * c.L * sizeof(float2);
-    b += (size_t)rec_lds * (sizeof(float2) + (c.D + 3) * sizeof(int32_t));
-    return b + 64 * sizeof(int);
-  }
-  // Lines, and a second buffer or the peel accumulator (2 (D+1) L values),
-  // twiddles; per record the amplitude, D frequency indices, output
-  // position, iteration and bin; the exchange words. The time-domain
-  // construction-subtraction accumulates the constructed spectra in a
-  // further (D+1) L values.
+// Threads per work-group of the solve kernels for D dimensions: the tuned
+// count, and for D >= 3 at least D+3 waves, so that two waves link records
+// while the D+1 line waves transform (3-D: 117 against 126 us on a 128^3
+// cube).
+int solve_threads(const fpssft_tuning& tn, int D) {
+  return D >= 3 ? std::max(tn.block_threads, std::min(512, 64 * (D + 3))) : tn.block_threads;
+}
+
+// The one-wave-per-line solve path: an eligible line and at least D+1 waves.
+bool uses_wave_path(const fpssft_tuning& tn, const CubeDesc& c) {
+  return wave_eligible(c) && solve_threads(tn, c.D) / 64 >= c.D + 1;
+}
+
+size_t solve_lds_bytes(const CubeDesc& c, int rec_cap, bool wave) {
+  // The layout of carve_solve_lds: the D+1 spectra, and on the block path a
+  // second buffer (the FFT's) or, with long lines, one line of scratch that
+  // also holds the bin-list heads; the twiddles; the constructed spectra of
+  // the time-domain construction-subtraction; the heads (L ints, rounded to
+  // 8 bytes); per record slot the set entry and the detection; the exchange
+  // words and counters.
   const size_t lines = (size_t)(c.D + 1) * c.L;
-  size_t b = (2 * lines + c.L + ((c.flags & FPS_LITERAL_PEEL) ? lines : 0)) * sizeof(float2);
-  b += (size_t)rec_lds * (sizeof(float2) + (c.D + 3) * sizeof(int32_t));
+  size_t b;
+  if (c.serial) {
+    b = (lines + c.L) * sizeof(float2);
+  } else {
+    b = (lines + (wave ? 0 : lines) + c.L + ((!wave && (c.flags & FPS_LITERAL_PEEL)) ? lines : 0)) * sizeof(float2);
+    b += (size_t)((c.L + 1) & ~1) * sizeof(int);
+  }
+  b += (size_t)rec_cap * FPS_REC_SLOT_BYTES(c.D);
   b += 64 * sizeof(int);
   return b;
 }
@@ -306,18 +322,10 @@ size_t lines_single_lds_bytes(const CubeDesc& c) {
   return c.serial ? 2 * (size_t)c.L * sizeof(float2) : lines_lds_bytes(c.D, c.L);
 }
 
-// Threads per work-group of the solve kernels for D dimensions: the tuned
-// count, and for D >= 3 at least D+3 waves, so that two waves peel while
-// the D+1 line waves transform (3-D: 117 against 126 us on a 128^3 cube).
-int solve_threads(const fpssft_tuning& tn, int D) {
-  return D >= 3 ? std::max(tn.block_threads, std::min(512, 64 * (D + 3))) : tn.block_threads;
-}
-
 fpssft::KernelKey key_of(const fpssft_plan_t p, int c) {
   const CubeDesc& cd = p->descs[c];
   const bool pow2 = cd.Lmask >= 0;
-  const bool wave = wave_eligible(cd) && solve_threads(p->tune, cd.D) / 64 >= cd.D + 1;
-  return fpssft::KernelKey{cd.D, pow2, p->rec_lds, wave};
+  return fpssft::KernelKey{cd.D, pow2, cd.rec_lds > 0, uses_wave_path(p->tune, cd)};
 }
 
 void destroy_plan(fpssft_plan_t p) {
@@ -338,6 +346,7 @@ void destroy_plan(fpssft_plan_t p) {
   hipFree(p->d_sched);
   hipFree(p->d_tw);
   hipFree(p->d_pre);
+  hipFree(p->d_recws);
   hipFree(p->d_order);
   hipFree(p->d_queue);
   hipFree(p->d_items);
@@ -384,6 +393,7 @@ fpssft_status build_plan(const fpssft_desc* descs, int32_t batch, const fpssft_t
   std::map<int32_t, int32_t> tw_off;
   p->descs.resize(batch);
   int64_t max_pre = 0;
+  int64_t rec_ws_bytes = 0;
   for (int32_t c = 0; c < batch; ++c) {
     const fpssft_desc& d = descs[c];
     int32_t L, T;
@@ -435,19 +445,27 @@ fpssft_status build_plan(const fpssft_desc* descs, int32_t batch, const fpssft_t
     // Lines too long for the D+1 spectra plus a second buffer and the
     // twiddles in LDS are transformed one at a time (no precomputed chunk).
     cd.serial = 0;
-    if (!wave_eligible(cd) && solve_lds_bytes(cd, 0) > p->lds_max) cd.serial = 1;
+    cd.rec_off = -1;
+    if (!wave_eligible(cd) && solve_lds_bytes(cd, 0, false) > p->lds_max) cd.serial = 1;
     if (cd.serial && (cd.flags & FPS_LITERAL_PEEL)) return FPSSFT_ERR_UNSUPPORTED;
     // the time-domain construction-subtraction needs the samples themselves
     const int32_t pre_T = (cd.serial || (cd.flags & FPS_LITERAL_PEEL)) ? 0 : std::min(T, tn.chunk_iters);
     max_pre = std::max<int64_t>(max_pre, (int64_t)pre_T * (d.ndim + 1) * L);
     p->max_N = std::max(p->max_N, cd.N);
-    if (solve_lds_bytes(cd, 0) > p->lds_max || lines_single_lds_bytes(cd) > p->lds_max)
+    const bool wave = uses_wave_path(tn, cd);
+    if (solve_lds_bytes(cd, 0, wave) > p->lds_max || lines_single_lds_bytes(cd) > p->lds_max)
       return FPSSFT_ERR_UNSUPPORTED;
-    // The record list stays in LDS when every cube's spectra and records fit.
-    if (solve_lds_bytes(cd, cd.max_k) > p->lds_max) p->rec_lds = false;
+    // The record store stays in LDS when the cube's spectra and records fit;
+    // otherwise it is a region of the plan's device workspace.
+    if (solve_lds_bytes(cd, cd.max_k, wave) <= p->lds_max) {
+      cd.rec_lds = cd.max_k;
+    } else {
+      cd.rec_lds = 0;
+      cd.rec_off = rec_ws_bytes;
+      rec_ws_bytes += ((int64_t)cd.max_k * FPS_REC_SLOT_BYTES(cd.D) + 255) / 256 * 256;
+    }
     p->descs[c] = cd;
   }
-  for (auto& cd : p->descs) cd.rec_lds = p->rec_lds ? cd.max_k : 0;
 
   // Group cubes by kernel instantiation; within a group, shortest lines
   // first, ties by index: short lines hold more sinusoids per bin, and their
@@ -483,7 +501,7 @@ fpssft_status build_plan(const fpssft_desc* descs, int32_t batch, const fpssft_t
       if (g.first < 0) g.first = i;
       ++g.count;
       const CubeDesc& cd = p->descs[order[i]];
-      g.lds_solve = std::max(g.lds_solve, solve_lds_bytes(cd, cd.rec_lds));
+      g.lds_solve = std::max(g.lds_solve, solve_lds_bytes(cd, cd.rec_lds, g.key.wave));
       g.lds_bwd = std::max(g.lds_bwd, bwd_lds_bytes(cd));
       g.max_N = std::max(g.max_N, cd.N);
     }
@@ -563,6 +581,7 @@ fpssft_status build_plan(const fpssft_desc* descs, int32_t batch, const fpssft_t
   HIP_TRY(hipMalloc(&p->d_tw, sizeof(float2) * p->tw.size()));
   HIP_TRY(hipMemcpy(p->d_tw, p->tw.data(), sizeof(float2) * p->tw.size(), hipMemcpyHostToDevice));
   if (max_pre > 0) HIP_TRY(hipMalloc(&p->d_pre, sizeof(float2) * max_pre));
+  if (rec_ws_bytes > 0) HIP_TRY(hipMalloc(&p->d_recws, (size_t)rec_ws_bytes));
   HIP_TRY(hipMalloc(&p->d_order, sizeof(int32_t) * batch));
   HIP_TRY(hipMemcpy(p->d_order, order.data(), sizeof(int32_t) * batch, hipMemcpyHostToDevice));
   // per group: the persistent solve's queue counter and exit counter (the
@@ -583,12 +602,13 @@ fpssft_status build_plan(const fpssft_desc* descs, int32_t batch, const fpssft_t
   p->ctx.descs = p->d_descs;
   p->ctx.sched = p->d_sched;
   p->ctx.tw = p->d_tw;
+  p->ctx.rec_ws = p->d_recws;
   HIP_TRY(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
   return FPSSFT_OK;
 }
 
 bool check_out(const fpssft_out* o) {
-  return o && o->freqs && o->amps && o->rec_iter && o->rec_bin && o->info;
+  return o && o->freqs && o->amps && o->rec_iter && o->rec_bin && o->rec_sin && o->info;
 }
 
 OutPtrs to_ptrs(const fpssft_out& o) {
@@ -597,6 +617,7 @@ OutPtrs to_ptrs(const fpssft_out& o) {
   p.amps = o.amps;
   p.rec_iter = o.rec_iter;
   p.rec_bin = o.rec_bin;
+  p.rec_sin = o.rec_sin;
   p.info = o.info;
   return p;
 }
@@ -656,6 +677,10 @@ fpssft_status fpssft_plan_create(const fpssft_desc* descs, int32_t batch, const 
   }
   *plan = p;
   return FPSSFT_OK;
+}
+
+fpssft_status fpssft_plan(const fpssft_desc* descs, int32_t batch, fpssft_plan_t* plan) {
+  return fpssft_plan_create(descs, batch, nullptr, plan);
 }
 
 fpssft_status fpssft_plan_destroy(fpssft_plan_t plan) {

@@ -8,6 +8,11 @@
 #define FPS_AXIS_SCHEDULE 0x1u
 #define FPS_AMP_AVERAGE 0x2u
 #define FPS_LITERAL_PEEL 0x4u
+#define FPS_DETERMINISTIC 0x8u
+
+// Output info words (fpssft_out.info): set size, iterations, outcome,
+// detections, merged frequencies left out of the set.
+#define FPS_INFO_LEN 8
 
 // Everything a kernel needs to know about one cube. Built on the host,
 // uploaded once per plan, read through scalar loads on the device.
@@ -36,6 +41,8 @@ struct CubeDesc {
   uint32_t flags;            // FPSSFT_FLAG_* of the description
   int32_t pad1;
   int64_t spec_off;          // element offset in the packed spectra buffer
+  int64_t rec_off;           // byte offset of the record store in the plan's
+                             // device workspace (rec_lds == 0), else -1
 };
 
 // Device pointers of one cube's outputs (same layout as fpssft_out).
@@ -44,8 +51,14 @@ struct OutPtrs {
   void* amps;
   int32_t* rec_iter;
   int32_t* rec_bin;
+  int32_t* rec_sin;
   int32_t* info;
 };
+
+// Bytes of one slot of a cube's record store (set entry + detection):
+// amplitude, D frequency indices, canonical set index, bin-list link,
+// detection iteration, bin and set index.
+#define FPS_REC_SLOT_BYTES(D) (8 + 4 * (D) + 5 * 4)
 
 // One work item of the line gather + FFT kernel: `count` iterations of one
 // cube starting at t0, written at element offset `out_off`.

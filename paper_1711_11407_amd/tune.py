@@ -57,9 +57,9 @@ def _time_ms(torch, fn, reps: int, warmup: int = 2) -> float:
 def _decisions(outs):
     import torch
     info = torch.stack([o.info for o in outs]).cpu()
-    sig = [tuple(info[c, :3].tolist()) for c in range(len(outs))]
-    freqs = [o.freqs[: int(info[c, 0])].cpu() for c, o in enumerate(outs)]
-    bins = [o.rec_bin[: int(info[c, 0])].cpu() for c, o in enumerate(outs)]
+    sig = [tuple(info[c, :5].tolist()) for c in range(len(outs))]
+    freqs = [o.freqs[: int(info[c, 0]) + int(info[c, 4])].cpu() for c, o in enumerate(outs)]
+    bins = [o.rec_bin[: int(info[c, 3])].cpu() for c, o in enumerate(outs)]
     return sig, freqs, bins
 
 

@@ -38,7 +38,7 @@ def test_execute_argument_errors(setup):
     assert lib.fpssft_execute(plan._h, -1, x, C.byref(o), None) == INVALID
     assert lib.fpssft_execute(plan._h, 0, None, C.byref(o), None) == INVALID
     assert lib.fpssft_execute(plan._h, 0, x, None, None) == INVALID
-    for field in ("freqs", "amps", "rec_iter", "rec_bin", "info"):
+    for field in ("freqs", "amps", "rec_iter", "rec_bin", "rec_sin", "info"):
         bad = outs[0].c_out()
         setattr(bad, field, None)
         assert lib.fpssft_execute(plan._h, 0, x, C.byref(bad), None) == INVALID, field

@@ -5,7 +5,7 @@ import pytest
 
 import oracle as O
 import workloads as W
-from gpu_common import compare, log, oracle_for, spec_for, torch_dev
+from gpu_common import compare, log, oracle_for, oracle_pool, spec_for, torch_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -72,27 +72,42 @@ def test_dot_product_identity(F):
 
 def test_cfg5_batched_backward(F):
     """Differentiation workload: 64 cubes of 256x256, K=50; batched forward
-    and backward; every cube's gradient equals the single-cube adjoint, and
-    a sample is checked against the FP64 finite differences."""
+    and backward. Every cube's records equal the oracle's, every cube's
+    gradient equals the FP64 reference gradient 2 M^H a (M: the oracle's
+    linear map from samples to set amplitudes with its decisions fixed) and
+    is zero off the touched line samples; two cubes are also checked against
+    FP64 finite differences, and each gradient equals the single-cube
+    adjoint's."""
     torch, dev = torch_dev()
     cubes = W.cfg5()
     specs = [spec_for(F, c.dims, c.schedule_seed, max_k=128) for c in cubes]
     plan = F.Plan(specs)
+    log("oracle and reference gradients over 64 cubes (process pool)")
+    refs = oracle_pool([("cfg5", c, plan.max_iters(c), 128, True) for c in range(len(cubes))])
     xs = [torch.from_numpy(c.x).to(dev).requires_grad_(True) for c in cubes]
     outs = F.sft_amplitudes_batched(plan, xs)
     loss = sum((a.abs() ** 2).sum() for a, _, _ in outs)
     loss.backward()
-    for c in (0, 17, 63):
-        ref, al, ta = oracle_for(plan, c, cubes[c].x, specs[c])
-        a, f, info = outs[c]
-        got = dict(k=int(info[0]), iters=int(info[1]), status=int(info[2]),
-                   freqs=f[:int(info[0])].cpu().numpy(), amps=a[:int(info[0])].detach().cpu().numpy(),
-                   rec_iter=ref.rec_iter, rec_bin=ref.rec_bin)
-        compare(got, ref, f"cfg5 cube {c}")
-        gref, _ = fd_reference(cubes[c].x, ref, al, ta)
-        g = xs[c].grad.cpu().numpy().astype(np.complex128)
+    res = plan.execute_batched([x.detach() for x in xs])
+    worst = 0.0
+    for c in range(len(cubes)):
+        ref, (pos, gpos) = refs[c]
+        compare(res[c].host(), ref, f"cfg5 cube {c}")
+        g = xs[c].grad.cpu().numpy().astype(np.complex128).reshape(-1)
+        gref = np.zeros_like(g)
+        gref[pos] = gpos
         err = np.linalg.norm(g - gref) / np.linalg.norm(gref)
         assert err <= GRAD_TOL, (c, err)
+        worst = max(worst, err)
+        mask = np.ones(g.size, bool)
+        mask[pos] = False
+        assert np.all(g[mask] == 0), c
+    log(f"cfg5: 64 gradients, worst rel L2 against 2 M^H a {worst:.1e}")
+    for c in (0, 63):
+        ref, al, ta = oracle_for(plan, c, cubes[c].x, specs[c])
+        gfd, _ = fd_reference(cubes[c].x, ref, al, ta)
+        g = xs[c].grad.cpu().numpy().astype(np.complex128)
+        assert np.linalg.norm(g - gfd) / np.linalg.norm(gfd) <= GRAD_TOL, c
         single = plan.execute(c, xs[c].detach())
         g1 = plan.amp_backward(c, single, 2 * single.amps).cpu().numpy()
         np.testing.assert_allclose(g1, g, rtol=0, atol=1e-5 * np.abs(g).max())
@@ -116,3 +131,27 @@ def test_bound_backward_equals_plan_backward(F):
         got = [g.cpu().numpy() for g in bound.run_backward()]
         for a, b in zip(got, ref):
             np.testing.assert_array_equal(a, b)
+
+
+def test_amp_backward_with_redetection(F):
+    """Cube 148 of the batched workload holds a frequency detected twice
+    (its two detections cancel and it leaves the set): the gradient of
+    sum |a|^2 over the set equals the FP64 reference 2 M^H a, where M is the
+    oracle's map from samples to the merged set amplitudes."""
+    torch, dev = torch_dev()
+    cube = W.cfg4(only=[148])[0]
+    spec = spec_for(F, cube.dims, cube.schedule_seed, max_k=512)
+    plan = F.Plan([spec])
+    x = torch.from_numpy(cube.x).to(dev).requires_grad_(True)
+    amps, freqs, info = F.sft_amplitudes(plan, 0, x)
+    assert int(info[3]) == int(info[0]) + 2 and int(info[4]) == 1
+    (amps.abs() ** 2).sum().backward()
+    g = x.grad.cpu().numpy().astype(np.complex128).reshape(-1)
+    ref, al, ta = oracle_for(plan, 0, cube.x, spec)
+    pos = O.touched_positions(cube.dims, ref.rec_iter, al, ta)
+    M = O.amp_matrix(cube.dims, ref, al, ta, pos)
+    gref = np.zeros_like(g)
+    gref[pos] = 2.0 * (M.conj().T @ ref.amps)
+    err = np.linalg.norm(g - gref) / np.linalg.norm(gref)
+    log(f"re-detection cube: {len(pos)} touched samples, grad rel L2 err={err:.2e}")
+    assert err <= GRAD_TOL

@@ -111,7 +111,7 @@ def test_iteration_cap_and_capacity(F):
     plan, got = run_plain(F, cube.x, spec)
     ref, _, _ = oracle_for(plan, 0, cube.x, spec)
     compare(got, ref, "capacity")
-    assert got["status"] == O.STATUS_CAPACITY and got["k"] == 10
+    assert got["status"] == O.STATUS_CAPACITY and got["n"] == 10
 
 
 def test_deadlock_axis_schedule(F):

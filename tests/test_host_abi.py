@@ -37,7 +37,10 @@ def test_library_exports_every_declared_symbol(F):
     for n in names:
         assert hasattr(lib, n), n
     assert {s[0] for s in _binding.SIGNATURES} == set(names)
-    assert lib.fpssft_abi_version() == 2
+    assert lib.fpssft_abi_version() == 3
+    # the calls the problem statement's boundary names
+    for n in ("fpssft_plan", "fpssft_execute", "fpssft_execute_batched", "fpssft_amp_backward"):
+        assert n in names, n
 
 
 def test_validate_line_length_and_budget(F):
@@ -91,10 +94,12 @@ def test_axis_schedule_matches_oracle_generator(F, dims):
 def test_unknown_flag_rejected(F):
     import ctypes as C
     from paper_1711_11407_amd import _binding as B
-    d, _keep = F.CubeSpec((8, 8), amp_average=True, literal_peel=True, axis_schedule=True).to_c()
-    assert d.flags == 0x7 and B.lib().fpssft_validate(C.byref(d), None, None) == 0
-    d.flags = 0x8
-    assert B.lib().fpssft_validate(C.byref(d), None, None) == -1
+    d, _keep = F.CubeSpec((8, 8), amp_average=True, literal_peel=True, axis_schedule=True,
+                          deterministic=True).to_c()
+    assert d.flags == 0xF and B.lib().fpssft_validate(C.byref(d), None, None) == 0
+    for bad in (0x10, 0x80000000):
+        d.flags = bad
+        assert B.lib().fpssft_validate(C.byref(d), None, None) == -1
 
 
 def test_workload_schedules_match(F):
