@@ -19,7 +19,14 @@ K = 5 N0 (uniform; clustered cases similar), 0% at K = 6 N0 with
 T_max = 85, and 5.9% of the samples at K = N0. Inputs are synthetic (the
 paper's are too); no dataset is used.
 
-    python fig2.py --runs 100 [--out results.json]
+--schedule axis runs the same sweep on the axis-aligned lines of the
+row/column method that Sec. 2.1 reviews and Sec. 2.2 shows to deadlock
+(iteration t samples along e_{t mod 2}); --schedule both prints the two
+curves side by side. Only the line set changes: decode, thresholds and
+budget are FPS-SFT's, so the comparison isolates the effect of random
+slopes.
+
+    python fig2.py --runs 100 [--schedule random|axis|both] [--out results.json]
 """
 from __future__ import annotations
 
@@ -65,7 +72,7 @@ def perfect(host: dict, cube) -> bool:
 
 
 def sweep(Ks=K_GRID, runs: int = 100, clusters=SCENARIOS, seed: int = 2017, tuning=None,
-          reps: int = 3, log=print):
+          reps: int = 3, log=print, axis: bool = False):
     """Plant, solve in one batched launch, and summarise. Returns a dict with
     the per-point table, the per-cube host results and the launch time."""
     import torch
@@ -76,7 +83,8 @@ def sweep(Ks=K_GRID, runs: int = 100, clusters=SCENARIOS, seed: int = 2017, tuni
     log(f"planted {len(cubes)} cubes of {DIMS} in {time.perf_counter() - t0:.1f} s")
     dev = torch.device("cuda", 0)
     max_k = int(2 ** np.ceil(np.log2(max(Ks) + 1)))
-    specs = [F.CubeSpec(DIMS, seed=c.schedule_seed, max_k=max_k, **W.NOISELESS_THRESH) for c in cubes]
+    specs = [F.CubeSpec(DIMS, seed=c.schedule_seed, max_k=max_k, axis_schedule=axis, **W.NOISELESS_THRESH)
+             for c in cubes]
     plan = F.Plan(specs, tuning=tuning)
     xs = [torch.from_numpy(c.x).to(dev) for c in cubes]
     bound = plan.bind(xs)
@@ -111,20 +119,36 @@ def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--runs", type=int, default=100)
     ap.add_argument("--seed", type=int, default=2017)
-    ap.add_argument("--out", default=None, help="write the table as JSON")
+    ap.add_argument("--schedule", choices=["random", "axis", "both"], default="random",
+                    help="line slopes: FPS-SFT's random ones, axis-aligned ones, or both sweeps")
+    ap.add_argument("--out", default=None, help="write the table(s) as JSON")
     args = ap.parse_args(argv)
-    res = sweep(runs=args.runs, seed=args.seed, log=lambda m: print(m, flush=True))
-    print(f"{'support':>10} {'K/N0':>6} {'P(perfect)':>11} {'% samples':>10}")
-    for row in res["table"]:
-        sup = "uniform" if row["cluster"] == 0 else f"cluster {row['cluster']}"
-        pct = "-" if row["pct_samples"] is None else f"{row['pct_samples']:.2f}"
-        print(f"{sup:>10} {row['K_over_N0']:>6.2f} {row['p_perfect']:>11.2f} {pct:>10}")
-    summary = {"dims": DIMS, "T_max": 85, "runs": args.runs, "seed": args.seed, "table": res["table"],
-               "cubes": res["cubes"], "ms_per_launch": round(res["ms_per_launch"], 3)}
+    kinds = ["random", "axis"] if args.schedule == "both" else [args.schedule]
+    results = {}
+    for kind in kinds:
+        results[kind] = sweep(runs=args.runs, seed=args.seed, axis=(kind == "axis"),
+                              log=lambda m: print(m, flush=True))
+    head = f"{'support':>10} {'K/N0':>6}"
+    for kind in kinds:
+        head += f" {kind + ' P':>10} {kind + ' %smp':>12}"
+    print(head)
+    rows = zip(*[results[k]["table"] for k in kinds])
+    for row in rows:
+        sup = "uniform" if row[0]["cluster"] == 0 else f"cluster {row[0]['cluster']}"
+        line = f"{sup:>10} {row[0]['K_over_N0']:>6.2f}"
+        for r in row:
+            pct = "-" if r["pct_samples"] is None else f"{r['pct_samples']:.2f}"
+            line += f" {r['p_perfect']:>10.2f} {pct:>12}"
+        print(line)
+    summary = {"dims": DIMS, "T_max": 85, "runs": args.runs, "seed": args.seed}
+    for kind in kinds:
+        summary[kind] = {"table": results[kind]["table"], "cubes": results[kind]["cubes"],
+                         "ms_per_launch": round(results[kind]["ms_per_launch"], 3)}
     if args.out:
         with open(args.out, "w") as f:
             json.dump(summary, f, indent=1)
-    print(json.dumps({k: v for k, v in summary.items() if k != "table"}), flush=True)
+    print(json.dumps({k: {kk: vv for kk, vv in v.items() if kk != "table"} if isinstance(v, dict) else v
+                      for k, v in summary.items()}), flush=True)
 
 
 if __name__ == "__main__":

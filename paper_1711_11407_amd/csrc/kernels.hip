@@ -253,10 +253,12 @@ struct SolveLds {
   float2* tw;    // [L] twiddles W_L^k (long lines: none, read from memory)
   int* head;     // [L] first set entry of each bin's list (long lines: in
                  // the scratch line, once the transforms are done)
+  uint32_t* bmax;  // [L] largest amplitude component of each bin's list
+                   // (float bits; next to the heads)
   RecStore rec;  // the record store when it is in LDS
   int* wsum;     // [2][16] per-wave exchange words, double-buffered
-  int* cnt;      // [4]: slots appended; largest amplitude component (float
-                 // bits); set size after a pass that filled the store
+  int* cnt;      // [4]: slots appended; unused; set size after a pass that
+                 // filled the store
 };
 
 // Layout (the host's solve_lds_bytes mirrors it): the wave path keeps the
@@ -274,6 +276,7 @@ __device__ __forceinline__ SolveLds carve_solve_lds(char* smem, int L, int rec_c
     s.bufB = s.bufA + (D + 1) * L;
     s.tw = nullptr;
     s.head = (int*)s.bufB;
+    s.bmax = (uint32_t*)(s.head + L);
     end = s.bufB + L;
   } else {
     if constexpr (kWave) {
@@ -289,7 +292,8 @@ __device__ __forceinline__ SolveLds carve_solve_lds(char* smem, int L, int rec_c
       end += (D + 1) * L;
     }
     s.head = (int*)end;
-    end = (float2*)(s.head + ((L + 1) & ~1));
+    s.bmax = (uint32_t*)(s.head + ((L + 1) & ~1));
+    end = (float2*)(s.bmax + ((L + 1) & ~1));
   }
   s.rec = carve_records<D>((char*)end, rec_cap);
   s.wsum = (int*)((char*)end + (size_t)rec_cap * FPS_REC_SLOT_BYTES(D));
@@ -297,20 +301,18 @@ __device__ __forceinline__ SolveLds carve_solve_lds(char* smem, int L, int rec_c
   return s;
 }
 
-// Exact, order-independent sums of the records' projections: each term is
-// converted to a 64-bit integer at scale 2^e (exact but for its bits below
-// 2^-e), the integers are added, and the sum is converted back once, so the
-// result does not depend on the order of the list. The scale is fixed per
-// iteration from the set size n and a bound on the amplitude components
-// (amax < 2^ea): a term is below sqrt(2) amax, a sum of at most n terms
-// below 2^(en + ea + 1) with n < 2^en, i.e. below 2^62 after scaling.
-__device__ __forceinline__ int fixed_exponent(int n, uint32_t amax_bits) {
-  const int en = 32 - __clz(n > 1 ? n : 1);
-  const int ea = (int)((amax_bits >> 23) & 0xffu) - 126;
-  return 61 - en - ea;
+// Exact, order-independent sums of the records' projections on one bin:
+// each term is truncated to an integer multiple of 2^-e in 32 bits, the
+// integers are added in 64 bits, and the sum is converted back once, so the
+// result does not depend on the order of a list. The scale comes from the
+// largest amplitude component in the bin's list (amax < 2^ea): a term is
+// below sqrt(2) amax < 2^(ea + 1), so e = 29 - ea keeps it below 2^30, and
+// the truncation error of a term is below 2^(ea - 29), about 4e-9 of amax.
+__device__ __forceinline__ int bin_exponent(uint32_t amax_bits) {
+  return 29 - ((int)((amax_bits >> 23) & 0xffu) - 126);
 }
-__device__ __forceinline__ long long to_fixed(float v, int e) { return (long long)__builtin_ldexp((double)v, e); }
-__device__ __forceinline__ float from_fixed(long long v, int e) { return (float)__builtin_ldexp((double)v, -e); }
+__device__ __forceinline__ long long fixed_term(float v, int e) { return (long long)(int)__builtin_ldexpf(v, e); }
+__device__ __forceinline__ float fixed_value(long long v, int e) { return (float)__builtin_ldexp((double)v, -e); }
 
 // Wave path of the solve loop (L = 64 E, 64 <= L <= 512, one wave per
 // line): wave w holds line w's values at l = lane + 64 e in registers.
@@ -368,20 +370,22 @@ __device__ __forceinline__ void wave_fft_to_lds(const float2 (&in)[kEMax], const
 // < n is linked into the list of its bin for this iteration's slope.
 template <int D, bool kPow2, bool kRecLds>
 __device__ __forceinline__ void link_bins(const Geo<D>& g, const uint32_t (&al)[D], const RecStore& rs, int* head,
-                                          int j0, int js, int n) {
+                                          uint32_t* bmax, int j0, int js, int n) {
   const uint32_t L = g.L;
   for (int j = j0; j < n; j += js) {
     uint32_t b = 0;
 #pragma unroll
     for (int k = 0; k < D; ++k)
       b = umod<kPow2>(b + al[k] * (g.c[k] * (uint32_t)rs_ld<kRecLds>(rs.sf, j * D + k)), L);
+    const float2 a = rs_ld<kRecLds>(rs.sa, j);
     rs_st<kRecLds>(rs.nx, j, atomicExch(&head[b], j));
+    atomicMax(&bmax[b], __float_as_uint(fmaxf(fabsf(a.x), fabsf(a.y))));
   }
 }
 
 // Then the thread that owns a bin sums its list's contributions on the D+1
-// lines (fixed point at scale 2^e, so the sum is the same for any list
-// order) into sum[i]. A list holds at most the n set entries, all with
+// lines (fixed point at scale 2^e from the bin's largest amplitude, so the
+// sum is the same for any list order) into sum[i]. A list holds at most the n set entries, all with
 // slots below n; the walk stops there whatever the links say.
 template <int D, bool kPow2, bool kRecLds>
 __device__ __forceinline__ void list_sum(const Geo<D>& g, const uint32_t (&ta)[D], const RecStore& rs,
@@ -401,20 +405,20 @@ __device__ __forceinline__ void list_sum(const Geo<D>& g, const uint32_t (&ta)[D
     }
     const float2 a = rs_ld<kRecLds>(rs.sa, j);
     float2 c = c_mulc(a, tw[p0]);
-    sr[0] += to_fixed(c.x, e);
-    si[0] += to_fixed(c.y, e);
+    sr[0] += fixed_term(c.x, e);
+    si[0] += fixed_term(c.y, e);
 #pragma unroll
     for (int k = 0; k < D; ++k) {
       uint32_t p = p0 + gk[k];
       if (p >= L) p -= L;
       c = c_mulc(a, tw[p]);
-      sr[k + 1] += to_fixed(c.x, e);
-      si[k + 1] += to_fixed(c.y, e);
+      sr[k + 1] += fixed_term(c.x, e);
+      si[k + 1] += fixed_term(c.y, e);
     }
     j = nxt;
   }
 #pragma unroll
-  for (int i = 0; i <= D; ++i) sum[i] = make_float2(from_fixed(sr[i], e), from_fixed(si[i], e));
+  for (int i = 0; i <= D; ++i) sum[i] = make_float2(fixed_value(sr[i], e), fixed_value(si[i], e));
 }
 
 // The set entry with frequency f in the list starting at h, or -1. A
@@ -511,7 +515,7 @@ template <int D, bool kPow2, bool kRecLds, bool kWave>
 __device__ __forceinline__ void solve_cube(const CubeDesc& cd, const float2* __restrict__ x, const OutPtrs out,
                                            const int32_t* __restrict__ sched, const float2* __restrict__ twall,
                                            const float2* __restrict__ pre, int pre_count, char* smem,
-                                           char* recws) {
+                                           char* rec_store) {
   const Geo<D> g = load_geo<D>(cd);
   const uint32_t L = g.L;
   const int T = cd.T;
@@ -531,11 +535,12 @@ __device__ __forceinline__ void solve_cube(const CubeDesc& cd, const float2* __r
   const bool literal = !(kWave && kPow2) && !serial && (cd.flags & FPS_LITERAL_PEEL) != 0;
   const bool avg = (cd.flags & FPS_AMP_AVERAGE) != 0;
   SolveLds s = carve_solve_lds<D, kWave>(smem, (int)L, kRecLds ? cd.rec_lds : 0, serial, literal);
-  const RecStore rs = kRecLds ? s.rec : carve_records<D>(recws + cd.rec_off, max_k);
+  const RecStore rs = kRecLds ? s.rec : carve_records<D>(rec_store, max_k);
   if (!serial) {
     for (uint32_t e = tid; e < L; e += B) {
       s.tw[e] = ld_g(twall, cd.tw_off + e);
       s.head[e] = -1;
+      s.bmax[e] = 0u;
     }
   }
   const float2* tw = serial ? twall + cd.tw_off : s.tw;
@@ -613,7 +618,7 @@ __device__ __forceinline__ void solve_cube(const CubeDesc& cd, const float2* __r
           wave_prefetch<D, kPow2>(pfw, E, g, x, at + 2 * D, pre + (int64_t)(t + 1) * (D + 1) * L, t + 1 < pre_count,
                                   wv);
       } else if (conc) {
-        link_bins<D, kPow2, kRecLds>(g, al, rs, s.head, tid - (D + 1) * 64, B - (D + 1) * 64, kc_set);
+        link_bins<D, kPow2, kRecLds>(g, al, rs, s.head, s.bmax, tid - (D + 1) * 64, B - (D + 1) * 64, kc_set);
       }
       rec_barrier<kRecLds>();
       S = s.bufA;
@@ -644,15 +649,14 @@ __device__ __forceinline__ void solve_cube(const CubeDesc& cd, const float2* __r
         // spectra (Eq. freqSum) go through an unnormalised inverse DFT, read
         // as the forward DFT at index (L - l) mod L, and are subtracted from
         // the samples (held divided by L, hence the constructed ones too).
-        link_bins<D, kPow2, kRecLds>(g, al, rs, s.head, tid, B, kc_set);
+        link_bins<D, kPow2, kRecLds>(g, al, rs, s.head, s.bmax, tid, B, kc_set);
         rec_barrier<kRecLds>();
-        const int fe = fixed_exponent(kc_set, (uint32_t)s.cnt[1]);
         for (uint32_t m = tid; m < L; m += B) {
           float2 sum[D + 1];
 #pragma unroll
           for (int i = 0; i <= D; ++i) sum[i] = make_float2(0.f, 0.f);
           const int h = s.head[m];
-          if (h >= 0) list_sum<D, kPow2, kRecLds>(g, ta, rs, tw, h, kc_set, fe, sum);
+          if (h >= 0) list_sum<D, kPow2, kRecLds>(g, ta, rs, tw, h, kc_set, bin_exponent(s.bmax[m]), sum);
 #pragma unroll
           for (int i = 0; i <= D; ++i) s.P[i * L + m] = sum[i];
         }
@@ -672,14 +676,15 @@ __device__ __forceinline__ void solve_cube(const CubeDesc& cd, const float2* __r
     if (!conc && !literal) {
       if (serial) {
         // the heads live in the scratch line, free once the lines are done
-        for (uint32_t e = tid; e < L; e += B) s.head[e] = -1;
+        for (uint32_t e = tid; e < L; e += B) {
+          s.head[e] = -1;
+          s.bmax[e] = 0u;
+        }
         lds_barrier();
       }
-      link_bins<D, kPow2, kRecLds>(g, al, rs, s.head, tid, B, kc_set);
+      link_bins<D, kPow2, kRecLds>(g, al, rs, s.head, s.bmax, tid, B, kc_set);
       rec_barrier<kRecLds>();
     }
-    // scale of this iteration's exact list sums
-    const int fe = fixed_exponent(kc_set, (uint32_t)s.cnt[1]);
 
     // Test, decode and record, bins in ascending order: a pass covers up to
     // kDecodeBins bins per thread (bin m0 + j B + tid for the j-th), with one
@@ -710,7 +715,7 @@ __device__ __forceinline__ void solve_cube(const CubeDesc& cd, const float2* __r
           const int h = s.head[m];
           if (h >= 0 && !literal) {
             float2 sum[D + 1];
-            list_sum<D, kPow2, kRecLds>(g, ta, rs, tw, h, kc_set, fe, sum);
+            list_sum<D, kPow2, kRecLds>(g, ta, rs, tw, h, kc_set, bin_exponent(s.bmax[m]), sum);
 #pragma unroll
             for (int i = 0; i <= D; ++i) r[i] = c_sub(r[i], sum[i]);
           }
@@ -718,6 +723,7 @@ __device__ __forceinline__ void solve_cube(const CubeDesc& cd, const float2* __r
           if (h >= 0) {
             if (cand[j]) mslot[j] = find_in_list<D, kRecLds>(rs, h, kc_set, f[j]);
             s.head[m] = -1;  // the list is rebuilt next iteration
+            s.bmax[m] = 0u;
           }
           isnew[j] = cand[j] && mslot[j] < 0;
         }
@@ -729,10 +735,21 @@ __device__ __forceinline__ void solve_cube(const CubeDesc& cd, const float2* __r
         bnew[j] = __popcll(bn & lt);
         wall += wnew[j];
       }
+      // New frequencies go to the store and detected ones join their entry
+      // now (one slot atomic per wave), so that the next iteration can link
+      // and sum them with no barrier after the exchange below. A merge that
+      // turns out not to fit the capacity is undone after the exchange.
+      float2 mold[kNB];
+#pragma unroll
+      for (int j = 0; j < kNB; ++j) {
+        mold[j] = make_float2(0.f, 0.f);
+        if (mslot[j] >= 0) {
+          mold[j] = rs_ld<kRecLds>(rs.sa, mslot[j]);
+          const float2 av = c_add(mold[j], amp[j]);
+          rs_st<kRecLds>(rs.sa, mslot[j], av);
+        }
+      }
       if (wall > 0) {
-        // New frequencies go to the store now (one atomic per wave), so that
-        // the next iteration can link them with no barrier after the
-        // exchange below.
         int base = 0;
         if (lane == 0) base = atomicAdd(&s.cnt[0], wall);
         base = __builtin_amdgcn_readlane(base, 0);
@@ -797,7 +814,6 @@ __device__ __forceinline__ void solve_cube(const CubeDesc& cd, const float2* __r
           const int di = kc_det + done_det + pdet[j] + bdet[j];
           if (di < max_k) {
             int si;
-            float2 av;
             if (isnew[j]) {
               si = kc_set + done_new + pnew[j] + bnew[j];
               int sl = slot[j];
@@ -812,18 +828,16 @@ __device__ __forceinline__ void solve_cube(const CubeDesc& cd, const float2* __r
                 atomicMax(&s.cnt[2], si + 1);
               }
               if (sl < max_k) rs_st<kRecLds>(rs.sp, sl, si);
-              av = amp[j];
             } else {
-              // detected again: the amplitude joins the first record
+              // detected again: the amplitude joined the first record
               si = rs_ld<kRecLds>(rs.sp, mslot[j]) & 0x7fffffff;
-              av = c_add(rs_ld<kRecLds>(rs.sa, mslot[j]), amp[j]);
-              rs_st<kRecLds>(rs.sa, mslot[j], av);
               rs_st<kRecLds>(rs.sp, mslot[j], (int32_t)((uint32_t)si | 0x80000000u));
             }
             rs_st<kRecLds>(rs.dt, di, t);
             rs_st<kRecLds>(rs.dm, di, (int32_t)(m0 + (uint32_t)(j * B) + tid));
             rs_st<kRecLds>(rs.ds, di, si);
-            atomicMax((unsigned int*)&s.cnt[1], __float_as_uint(fmaxf(fabsf(av.x), fabsf(av.y))));
+          } else if (!isnew[j]) {
+            rs_st<kRecLds>(rs.sa, mslot[j], mold[j]);
           }
         }
         done_det += tdet[j];
@@ -943,9 +957,9 @@ template <int D, bool kPow2, bool kRecLds, bool kWave>
 __global__ FPS_SOLVE_ATTRS void k_solve_plain(const CubeDesc* __restrict__ descs, int cube, const float2* __restrict__ x,
                                               OutPtrs out, const int32_t* __restrict__ sched,
                                               const float2* __restrict__ tw, const float2* __restrict__ pre,
-                                              int pre_count, char* recws) {
+                                              int pre_count, char* rec_store) {
   extern __shared__ __attribute__((aligned(16))) char lds_solve[];
-  solve_cube<D, kPow2, kRecLds, kWave>(descs[cube], x, out, sched, tw, pre, pre_count, lds_solve, recws);
+  solve_cube<D, kPow2, kRecLds, kWave>(descs[cube], x, out, sched, tw, pre, pre_count, lds_solve, rec_store);
 }
 
 // Persistent: every work-group loops taking the next cube of `order` from
@@ -975,7 +989,8 @@ __global__ FPS_SOLVE_ATTRS void k_solve_batched(const CubeDesc* __restrict__ des
       break;
     }
     const int c = __builtin_amdgcn_readfirstlane(order[idx]);
-    solve_cube<D, kPow2, kRecLds, kWave>(descs[c], xs[c], outs[c], sched, tw, nullptr, 0, lds_solve, recws);
+    solve_cube<D, kPow2, kRecLds, kWave>(descs[c], xs[c], outs[c], sched, tw, nullptr, 0, lds_solve,
+                                         kRecLds ? nullptr : recws + descs[c].rec_off);
   }
 }
 
@@ -1199,11 +1214,11 @@ hipError_t launch_lines_items(const LaunchCtx& ctx, const KernelKey& key, const 
 }
 
 hipError_t launch_solve_plain(const LaunchCtx& ctx, const KernelKey& key, int cube, const float2* x,
-                              const OutPtrs& out, const float2* pre, int pre_count, size_t lds, int threads,
-                              hipStream_t st) {
+                              const OutPtrs& out, const float2* pre, int pre_count, char* rec_store, size_t lds,
+                              int threads, hipStream_t st) {
   FPS_DISPATCH_SOLVE(key, {
     hipLaunchKernelGGL((k_solve_plain<kD, kP, kR, kW>), dim3(1), dim3(threads), lds, st, ctx.descs, cube, x, out,
-                       ctx.sched, ctx.tw, pre, pre_count, ctx.rec_ws);
+                       ctx.sched, ctx.tw, pre, pre_count, rec_store);
   })
   return hipGetLastError();
 }

@@ -37,8 +37,8 @@ hipError_t launch_lines_items(const LaunchCtx& ctx, const KernelKey& key, const 
                               const int32_t* ranges, int* queues, int grid, const float2* const* xs, float2* out,
                               int maxL, size_t lds, int threads, hipStream_t st);
 hipError_t launch_solve_plain(const LaunchCtx& ctx, const KernelKey& key, int cube, const float2* x,
-                              const OutPtrs& out, const float2* pre, int pre_count, size_t lds, int threads,
-                              hipStream_t st);
+                              const OutPtrs& out, const float2* pre, int pre_count, char* rec_store, size_t lds,
+                              int threads, hipStream_t st);
 hipError_t launch_reset(int* p, int n, hipStream_t st);
 hipError_t launch_solve_batched(const LaunchCtx& ctx, const KernelKey& key, const float2* const* xs,
                                 const OutPtrs* outs, const int32_t* order, int ncubes, int* queue, int grid,

@@ -294,17 +294,17 @@ bool uses_wave_path(const fpssft_tuning& tn, const CubeDesc& c) {
 size_t solve_lds_bytes(const CubeDesc& c, int rec_cap, bool wave) {
   // The layout of carve_solve_lds: the D+1 spectra, and on the block path a
   // second buffer (the FFT's) or, with long lines, one line of scratch that
-  // also holds the bin-list heads; the twiddles; the constructed spectra of
-  // the time-domain construction-subtraction; the heads (L ints, rounded to
-  // 8 bytes); per record slot the set entry and the detection; the exchange
-  // words and counters.
+  // also holds the bin-list words; the twiddles; the constructed spectra of
+  // the time-domain construction-subtraction; the bin-list heads and
+  // largest amplitudes (2 x L ints, each rounded to 8 bytes); per record
+  // slot the set entry and the detection; the exchange words and counters.
   const size_t lines = (size_t)(c.D + 1) * c.L;
   size_t b;
   if (c.serial) {
     b = (lines + c.L) * sizeof(float2);
   } else {
     b = (lines + (wave ? 0 : lines) + c.L + ((!wave && (c.flags & FPS_LITERAL_PEEL)) ? lines : 0)) * sizeof(float2);
-    b += (size_t)((c.L + 1) & ~1) * sizeof(int);
+    b += 2 * (size_t)((c.L + 1) & ~1) * sizeof(int);
   }
   b += (size_t)rec_cap * FPS_REC_SLOT_BYTES(c.D);
   b += 64 * sizeof(int);
@@ -721,7 +721,8 @@ fpssft_status fpssft_execute(fpssft_plan_t p, int32_t cube, const void* x, const
     HIP_TRY(fpssft::launch_lines_single(p->ctx, key, cube, (const float2*)x, 0, pre, p->d_pre, cd.L,
                                         lines_single_lds_bytes(cd), p->tune.lines_threads, st));
   }
-  HIP_TRY(fpssft::launch_solve_plain(p->ctx, key, cube, (const float2*)x, to_ptrs(*out), p->d_pre, pre,
+  char* rec = cd.rec_lds ? nullptr : p->d_recws + cd.rec_off;
+  HIP_TRY(fpssft::launch_solve_plain(p->ctx, key, cube, (const float2*)x, to_ptrs(*out), p->d_pre, pre, rec,
                                      g.lds_solve, g.threads, st));
   return FPSSFT_OK;
 }

@@ -53,3 +53,27 @@ def test_fig2_sampled_cubes_match_the_oracle(sweeps):
             compare(res["hosts"][i], ref, f"fig2 cluster {cl} K={K} run {r}")
             if ref.status == O.STATUS_OK:
                 assert {tuple(f) for f in ref.freqs.tolist()} == {tuple(f) for f in cube.freqs.tolist()}
+
+
+def test_fig2_axis_schedule_comparison_curve():
+    """The comparison curve: the same sweep on the axis-aligned lines of the
+    row/column method (Sec. 2.1), which Sec. 2.2 shows to deadlock on
+    grid-like supports. With FPS-SFT's decode on those lines, recovery holds
+    only for the sparsest uniform supports and fails at K = 2 N0 and with a
+    cluster, while random slopes recover every one of the same cubes (the
+    behaviour Sec. 3 reports for the comparison method)."""
+    import fig2
+    axis = fig2.sweep(Ks=(128, 512), runs=16, clusters=(0, 9), seed=13, reps=1, log=log, axis=True)
+    rnd = fig2.sweep(Ks=(128, 512), runs=16, clusters=(0, 9), seed=13, reps=1, log=log)
+    for r in axis["table"]:
+        log(f"axis: cluster {r['cluster']} K={r['K']}: P(perfect) {r['p_perfect']:.2f}")
+    assert _point(axis, 0, 128)["p_perfect"] >= 0.75
+    assert _point(axis, 0, 512)["p_perfect"] == 0.0
+    assert _point(axis, 9, 128)["p_perfect"] <= 0.1
+    for r in rnd["table"]:
+        assert r["p_perfect"] == 1.0, r
+    plan = axis["plan"]
+    for i in (0, 16, 32):
+        cube = axis["planted"][i]
+        ref, _, _ = oracle_for(plan, i, cube.x, plan.specs[i])
+        compare(axis["hosts"][i], ref, f"axis sweep cube {i}")
