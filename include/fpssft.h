@@ -273,6 +273,21 @@ int64_t fpssft_plan_spectra_elems(fpssft_plan_t plan);
 fpssft_status fpssft_execute(fpssft_plan_t plan, int32_t cube, const void* x,
                              const fpssft_out* out, void* stream);
 
+/* fpssft_execute for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same launches with the same results, bit for bit, but the
+ * pre-chunk spectra and a record store that does not fit in LDS come from a
+ * static device array of 4 MiB (one per GPU, held until the process ends)
+ * instead of the plan's workspace. The call allocates nothing. Every call on
+ * a GPU shares that GPU's array: calls that overlap on one GPU (concurrent
+ * streams, other threads) race and must be ordered by the caller. Nothing in
+ * the array needs to start at zero. UNSUPPORTED when the cube needs more
+ * than 4 MiB: chunk_iters (D+1) L * 8 bytes rounded up to 256, plus max_k
+ * (28 + 4 D) bytes when the records exceed LDS. Argument errors as for
+ * fpssft_execute. */
+fpssft_status fpssft_execute_noalloc(fpssft_plan_t plan, int32_t cube, const void* x,
+                                     const fpssft_out* out, void* stream);
+
 /* The same method (Sec. 2.2) for all cubes of the plan in one persistent
  * launch per kernel instantiation (work-groups take cubes from a device
  * queue, shortest lines first), replayed from a HIP graph or launched

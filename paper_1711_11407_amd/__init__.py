@@ -238,6 +238,16 @@ class Plan:
                                        _stream_ptr(stream)), "execute")
         return out
 
+    def execute_noalloc(self, cube: int, x, out: Result, stream=None) -> Result:
+        """fpssft_execute_noalloc: the plain path with its scratch in the
+        library's static device array (no device allocation in the call;
+        the caller provides the outputs)."""
+        self._check_x(cube, x)
+        o = out.c_out()
+        B.check(B.lib().fpssft_execute_noalloc(self._h, cube, C.c_void_p(x.data_ptr()), C.byref(o),
+                                               _stream_ptr(stream)), "execute_noalloc")
+        return out
+
     def execute_batched(self, xs, outs: Optional[Sequence[Result]] = None, stream=None):
         """All cubes in one persistent launch per kernel instantiation, replayed
         from a HIP graph or launched directly (fpssft_execute_batched)."""

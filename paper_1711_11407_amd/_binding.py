@@ -71,6 +71,7 @@ SIGNATURES = [
                                           C.POINTER(C.c_int32), C.POINTER(C.c_int64)]),
     ("fpssft_plan_spectra_elems", C.c_int64, [C.c_void_p]),
     ("fpssft_execute", C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.POINTER(Out), C.c_void_p]),
+    ("fpssft_execute_noalloc", C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.POINTER(Out), C.c_void_p]),
     ("fpssft_execute_batched", C.c_int32, [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(Out), C.c_void_p]),
     ("fpssft_lines_fft", C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.c_int32,
                                      C.c_void_p, C.c_void_p]),

@@ -24,6 +24,8 @@
 // path); the host groups cubes by instantiation.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "device.h"
 #include "launch.h"
 
@@ -1191,6 +1193,35 @@ const void* kernel_ptr(KernelKind kind, const KernelKey& key) {
     fn = kind == KernelKind::kLines ? (const void*)k_lines<kD, kP> : (const void*)k_backward<kD, kP>;
   }))
   return fn;
+}
+
+// ---------------------------------------------------------------------------
+// Scratch of the allocation-free plain entry point: one static array, of
+// which every GPU the library runs on holds its own copy until the process
+// ends. Host code uses the address hipGetSymbolAddress returns for the
+// current device, never the array's name.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+hipError_t noalloc_scratch(int device, void** out) {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static void* addr[kMaxDevices] = {};
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[device]) {
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    if (cur != device) return hipErrorInvalidDevice;
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!ptr) return hipErrorInvalidSymbol;
+    addr[device] = ptr;
+  }
+  *out = addr[device];
+  return hipSuccess;
 }
 
 hipError_t launch_lines_single(const LaunchCtx& ctx, const KernelKey& key, int cube, const float2* x, int t0,

@@ -29,6 +29,15 @@ struct KernelKey {
 
 enum class KernelKind { kLines, kSolvePlain, kSolveBatched, kBackward };
 
+// The allocation-free plain entry point takes its scratch (the pre-chunk
+// spectra and a record store in device memory) from one static device
+// array per GPU of this many bytes.
+constexpr size_t kNoAllocScratchBytes = size_t(4) << 20;
+
+// Address of that array on `device`, which must be the current device;
+// looked up once per device (hipGetSymbolAddress) and cached.
+hipError_t noalloc_scratch(int device, void** out);
+
 const void* kernel_ptr(KernelKind kind, const KernelKey& key);
 
 hipError_t launch_lines_single(const LaunchCtx& ctx, const KernelKey& key, int cube, const float2* x, int t0,

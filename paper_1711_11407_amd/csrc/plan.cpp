@@ -254,6 +254,9 @@ struct fpssft_plan_st {
   float2* d_pre = nullptr;
   // record stores of the cubes whose records do not fit in LDS
   char* d_recws = nullptr;
+  // the static scratch array of the allocation-free entry point on this
+  // plan's device
+  void* noalloc_scratch = nullptr;
   // batched path
   int32_t* d_order = nullptr;
   int* d_queue = nullptr;
@@ -366,6 +369,8 @@ bool on_plan_device(const fpssft_plan_t p) {
 fpssft_status build_plan(const fpssft_desc* descs, int32_t batch, const fpssft_tuning* tuning,
                          fpssft_plan_t p) {
   HIP_TRY(hipGetDevice(&p->device));
+  // set-up of the allocation-free entry point's scratch on this device
+  HIP_TRY(fpssft::noalloc_scratch(p->device, &p->noalloc_scratch));
   int v = 0;
   HIP_TRY(hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, p->device));
   p->ncu = v;
@@ -723,6 +728,31 @@ fpssft_status fpssft_execute(fpssft_plan_t p, int32_t cube, const void* x, const
   }
   char* rec = cd.rec_lds ? nullptr : p->d_recws + cd.rec_off;
   HIP_TRY(fpssft::launch_solve_plain(p->ctx, key, cube, (const float2*)x, to_ptrs(*out), p->d_pre, pre, rec,
+                                     g.lds_solve, g.threads, st));
+  return FPSSFT_OK;
+}
+
+fpssft_status fpssft_execute_noalloc(fpssft_plan_t p, int32_t cube, const void* x, const fpssft_out* out,
+                                     void* stream) {
+  if (!p || cube < 0 || cube >= p->B || !x || !check_out(out)) return FPSSFT_ERR_INVALID_ARG;
+  if (!on_plan_device(p)) return FPSSFT_ERR_INVALID_ARG;
+  const CubeDesc& cd = p->descs[cube];
+  const int pre = (cd.serial || (cd.flags & FPS_LITERAL_PEEL)) ? 0 : std::min(cd.T, p->tune.chunk_iters);
+  // the pre-chunk spectra, then the record store when it is not in LDS
+  const size_t pre_span = ((size_t)pre * (cd.D + 1) * cd.L * sizeof(float2) + 255) / 256 * 256;
+  const size_t rec_bytes = cd.rec_lds ? 0 : (size_t)cd.max_k * FPS_REC_SLOT_BYTES(cd.D);
+  if (pre_span + rec_bytes > fpssft::kNoAllocScratchBytes) return FPSSFT_ERR_UNSUPPORTED;
+  char* base = (char*)p->noalloc_scratch;
+  float2* pre_buf = (float2*)base;
+  char* rec = cd.rec_lds ? nullptr : base + pre_span;
+  hipStream_t st = (hipStream_t)stream;
+  const fpssft::KernelKey key = key_of(p, cube);
+  const Group& g = p->groups[p->group_of[cube]];
+  if (pre > 0) {
+    HIP_TRY(fpssft::launch_lines_single(p->ctx, key, cube, (const float2*)x, 0, pre, pre_buf, cd.L,
+                                        lines_single_lds_bytes(cd), p->tune.lines_threads, st));
+  }
+  HIP_TRY(fpssft::launch_solve_plain(p->ctx, key, cube, (const float2*)x, to_ptrs(*out), pre_buf, pre, rec,
                                      g.lds_solve, g.threads, st));
   return FPSSFT_OK;
 }
