@@ -357,6 +357,9 @@ def main():
     ap.add_argument("--only", choices=["copy", "lines", "lines3d", "batched", "plain", "configs", "grad"],
                     default=None)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--lean", action="store_true",
+                    help="with --only: the warm timed launches alone (no cache-flushed or graph legs), "
+                         "for profiler passes")
     ap.add_argument("--traffic-from", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
                     help="write profiles/traffic.json from rocprofv3 --pmc output directories")
     args = ap.parse_args()
@@ -424,10 +427,10 @@ def main():
         # and the Infinity Cache; each launch timed on its own.
         scratch = torch.empty(1 << 26, dtype=torch.float64, device=dev)
         cold = []
-        for _ in range(max(3, args.steps // 4)):
+        for _ in range(0 if args.lean else max(3, args.steps // 4)):
             scratch.fill_(1.0)
             cold.append(event_time_ms(torch, bound.run_lines_all, 1))
-        cms = float(np.median(cold))
+        cms = float(np.median(cold)) if cold else float("nan")
         result["line_fft"]["cold_ms_per_launch"] = round(cms, 4)
         result["line_fft"]["cold_achieved"] = round(alg / (cms * 1e-3) / 1e9, 1)
         del scratch
@@ -480,14 +483,19 @@ def main():
         # find part of them cached); each step timed on its own.
         scratch = torch.empty(1 << 26, dtype=torch.float64, device=dev)
         cold = []
-        for _ in range(max(5, args.steps // 2)):
+        for _ in range(0 if args.lean else max(5, args.steps // 2)):
             scratch.fill_(1.0)
             cold.append(event_time_ms(torch, bound.run_batched, 1))
         del scratch
-        result["batched_cold"] = {"ms_per_step": round(float(np.median(cold)), 4),
-                                  "value": round(B / (float(np.median(cold)) * 1e-3), 1), "unit": "transforms/s",
-                                  "note": "median of single steps, each after a 512 MiB scratch write"}
-        log(f"batched, caches flushed: {float(np.median(cold)):.3f} ms/step")
+        if cold:
+            result["batched_cold"] = {"ms_per_step": round(float(np.median(cold)), 4),
+                                      "value": round(B / (float(np.median(cold)) * 1e-3), 1),
+                                      "unit": "transforms/s",
+                                      "note": "median of single steps, each after a 512 MiB scratch write"}
+            log(f"batched, caches flushed: {float(np.median(cold)):.3f} ms/step")
+        if args.lean:
+            log(json.dumps(result))
+            return
         # The same step replayed from the HIP graph (the other launch form).
         gplan = F.Plan(specs, tuning=dict(tuning or {}, direct_launch=0))
         gbound = gplan.bind(xs)

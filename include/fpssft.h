@@ -152,12 +152,26 @@ typedef struct {
   int32_t* info;
 } fpssft_out;
 
+/* Launch shapes for the cubes of one (D, L) class, chosen by the autotuner
+ * per class; 0 in a field keeps the plan-wide value of fpssft_tuning.
+ *  ndim, line_length  the class: cubes with D = ndim and L = line_length
+ *  block_threads      threads per work-group of the solve kernels
+ *  lines_samples      samples per work item of the line gather + FFT kernel */
+typedef struct {
+  int32_t ndim;
+  int32_t line_length;
+  int32_t block_threads;
+  int32_t lines_samples;
+} fpssft_shape_tuning;
+
 /* Launch-shape choices of the autotuner (0 = library default; chunk_iters
  * is taken as given when >= 0, so pass -1 for its default).
  *  block_threads  threads per work-group of the solve and adjoint kernels
  *                 (64..512, multiple of 64); for D >= 3 the solve kernels
- *                 use at least 64 (D+3), room for two peeling waves
- *  max_radix      largest FFT radix used for power-of-two factors (2, 4, 8)
+ *                 use at least 64 (D+3), room for two linking waves
+ *  max_radix      largest FFT radix of the block (LDS) transforms: the line
+ *                 gather + FFT kernel, and the solve kernels' lines that
+ *                 are not power-of-two lines of 64..512 points (2, 4, 8)
  *  chunk_iters    iterations the plain path gathers and transforms ahead
  *                 in parallel before its sequential decode (>= 0)
  *  lines_wg       consecutive iterations per work item of the persistent
@@ -170,7 +184,14 @@ typedef struct {
  *  lines_samples  > 0: a work item of the line kernel takes
  *                 max(1, lines_samples / ((D+1) L)) consecutive iterations
  *                 of its cube (about that many samples, whatever the line
- *                 length); < 0: lines_wg iterations; 0: default 3072 */
+ *                 length); < 0: lines_wg iterations; 0: default 3072
+ *  group_by_length  1: one persistent launch per kernel instantiation and
+ *                 line length (and launch shape); the launches of a call
+ *                 run concurrently (parallel branches of the graph, or
+ *                 side streams joined back to the caller's stream);
+ *                 0: one per kernel instantiation and launch shape
+ *  nshapes, shapes  per-(D, L) overrides (host array, copied by the plan;
+ *                 may be NULL when nshapes is 0) */
 typedef struct {
   int32_t block_threads;
   int32_t max_radix;
@@ -179,6 +200,9 @@ typedef struct {
   int32_t lines_threads;
   int32_t direct_launch;
   int32_t lines_samples;
+  int32_t group_by_length;
+  int32_t nshapes;
+  const fpssft_shape_tuning* shapes;
 } fpssft_tuning;
 
 typedef struct fpssft_plan_st* fpssft_plan_t;
@@ -219,9 +243,9 @@ fpssft_status fpssft_schedule_generate(const fpssft_desc* desc, int32_t T,
  * LDS (160 KB) are transformed one line at a time, with the twiddles read
  * from device memory; UNSUPPORTED when even the D+1 spectra plus one line of
  * scratch do not fit ((D+2) L * 8 bytes > 160 KB, e.g. L > 6800 for D = 2).
- * A cube's record store (max_k slots of 28 + 4 D bytes: set entry and
- * detection) stays in LDS when it fits beside the spectra, else the plan
- * allocates it in device memory. */
+ * A cube's record store (max_k slots of 16 + 4 D bytes, one per set entry)
+ * stays in LDS when it fits beside the spectra, else the plan allocates it
+ * in device memory. */
 fpssft_status fpssft_plan_create(const fpssft_desc* descs, int32_t batch,
                                  const fpssft_tuning* tuning, fpssft_plan_t* plan);
 
@@ -283,7 +307,7 @@ fpssft_status fpssft_execute(fpssft_plan_t plan, int32_t cube, const void* x,
  * streams, other threads) race and must be ordered by the caller. Nothing in
  * the array needs to start at zero. UNSUPPORTED when the cube needs more
  * than 4 MiB: chunk_iters (D+1) L * 8 bytes rounded up to 256, plus max_k
- * (28 + 4 D) bytes when the records exceed LDS. Argument errors as for
+ * (16 + 4 D) bytes when the records exceed LDS. Argument errors as for
  * fpssft_execute. */
 fpssft_status fpssft_execute_noalloc(fpssft_plan_t plan, int32_t cube, const void* x,
                                      const fpssft_out* out, void* stream);

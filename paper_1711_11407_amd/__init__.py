@@ -153,6 +153,7 @@ class Plan:
             descs[i] = d
             keep.append(k)
         tn = None
+        shapes = None
         if tuning:
             tn = B.Tuning()
             tn.block_threads = int(tuning.get("block_threads", 0))
@@ -163,6 +164,18 @@ class Plan:
             tn.direct_launch = int(tuning.get("direct_launch", 0))
             # an explicit lines_wg without lines_samples means lines_wg
             tn.lines_samples = int(tuning.get("lines_samples", -1 if "lines_wg" in tuning else 0))
+            tn.group_by_length = int(tuning.get("group_by_length", 0))
+            sh = tuning.get("shapes") or []
+            # per-(D, L) launch shapes: {"ndim", "line_length", "block_threads",
+            # "lines_samples"} (missing fields: plan-wide)
+            shapes = (B.ShapeTuning * max(1, len(sh)))()
+            for i, e in enumerate(sh):
+                shapes[i].ndim = int(e["ndim"])
+                shapes[i].line_length = int(e["line_length"])
+                shapes[i].block_threads = int(e.get("block_threads", 0))
+                shapes[i].lines_samples = int(e.get("lines_samples", 0))
+            tn.nshapes = len(sh)
+            tn.shapes = C.cast(shapes, C.POINTER(B.ShapeTuning))
         h = C.c_void_p()
         B.check(B.lib().fpssft_plan_create(descs, len(self.specs), C.byref(tn) if tn else None, C.byref(h)),
                 "plan_create")

@@ -45,6 +45,15 @@ class Out(C.Structure):
     ]
 
 
+class ShapeTuning(C.Structure):
+    _fields_ = [
+        ("ndim", C.c_int32),
+        ("line_length", C.c_int32),
+        ("block_threads", C.c_int32),
+        ("lines_samples", C.c_int32),
+    ]
+
+
 class Tuning(C.Structure):
     _fields_ = [
         ("block_threads", C.c_int32),
@@ -54,6 +63,9 @@ class Tuning(C.Structure):
         ("lines_threads", C.c_int32),
         ("direct_launch", C.c_int32),
         ("lines_samples", C.c_int32),
+        ("group_by_length", C.c_int32),
+        ("nshapes", C.c_int32),
+        ("shapes", C.POINTER(ShapeTuning)),
     ]
 
 

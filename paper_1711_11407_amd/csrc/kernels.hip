@@ -185,10 +185,10 @@ __global__ void k_lines(const CubeDesc* __restrict__ descs, const LineItem* __re
 // One cube, one work-group.
 // ---------------------------------------------------------------------------
 
-// Record store of one cube. The recovered set holds one slot per distinct
-// frequency, in the order the work-group's waves appended them; the
-// detection trace is in canonical (iteration, bin) order. The store lives in
+// Record store of one cube: the recovered set, one slot per distinct
+// frequency, in the order the work-group's waves appended them. It lives in
 // LDS (kRecLds) or in the plan's device workspace, `cap` entries per array.
+// The detection trace goes to the outputs as it is found.
 struct RecStore {
   float2* sa;   // [cap] amplitude of a set entry: the sum of its detections
   int32_t* sf;  // [cap][D] its frequency indices
@@ -197,9 +197,6 @@ struct RecStore {
   int32_t* nx;  // [cap] next entry projecting onto the same bin in this
                 // iteration (-1 ends a list); at the end of the cube, the
                 // slot, then the output position, of each canonical index
-  int32_t* dt;  // [cap] detection: iteration
-  int32_t* dm;  // [cap] detection: bin
-  int32_t* ds;  // [cap] detection: canonical set index of its frequency
 };
 
 template <int D>
@@ -209,9 +206,6 @@ __device__ __forceinline__ RecStore carve_records(char* base, int cap) {
   r.sf = (int32_t*)(r.sa + cap);
   r.sp = r.sf + cap * D;
   r.nx = r.sp + cap;
-  r.dt = r.nx + cap;
-  r.dm = r.dt + cap;
-  r.ds = r.dm + cap;
   return r;
 }
 
@@ -257,6 +251,9 @@ struct SolveLds {
                  // the scratch line, once the transforms are done)
   uint32_t* bmax;  // [L] largest amplitude component of each bin's list
                    // (float bits; next to the heads)
+  int* bcnt;     // [L] entries in each bin's list (not with long lines)
+  int2* Q;       // [(D+1) L] each bin's projection sums per line, fixed point
+                 // (not with long lines)
   RecStore rec;  // the record store when it is in LDS
   int* wsum;     // [2][16] per-wave exchange words, double-buffered
   int* cnt;      // [4]: slots appended; unused; set size after a pass that
@@ -266,8 +263,9 @@ struct SolveLds {
 // Layout (the host's solve_lds_bytes mirrors it): the wave path keeps the
 // D+1 spectra (each wave's transform writes its row), the block path two
 // line buffers; then the twiddles, the constructed spectra of the
-// time-domain construction-subtraction, the bin-list heads, the records and
-// the exchange words.
+// time-domain construction-subtraction, the per-bin words (list heads,
+// largest amplitudes, entry counts) and fixed-point projection sums, the
+// records and the exchange words.
 template <int D, bool kWave>
 __device__ __forceinline__ SolveLds carve_solve_lds(char* smem, int L, int rec_cap, bool serial, bool literal) {
   SolveLds s;
@@ -279,6 +277,8 @@ __device__ __forceinline__ SolveLds carve_solve_lds(char* smem, int L, int rec_c
     s.tw = nullptr;
     s.head = (int*)s.bufB;
     s.bmax = (uint32_t*)(s.head + L);
+    s.bcnt = nullptr;
+    s.Q = nullptr;
     end = s.bufB + L;
   } else {
     if constexpr (kWave) {
@@ -293,9 +293,14 @@ __device__ __forceinline__ SolveLds carve_solve_lds(char* smem, int L, int rec_c
       s.P = end;
       end += (D + 1) * L;
     }
+    const int Lr = (L + 1) & ~1;
     s.head = (int*)end;
-    s.bmax = (uint32_t*)(s.head + ((L + 1) & ~1));
-    end = (float2*)(s.bmax + ((L + 1) & ~1));
+    s.bmax = (uint32_t*)(s.head + Lr);
+    s.bcnt = (int*)(s.bmax + Lr);
+    // the time-domain construction-subtraction converts the sums into its
+    // constructed spectra in place
+    s.Q = s.P ? (int2*)s.P : (int2*)(s.bcnt + Lr);
+    end = s.P ? (float2*)(s.bcnt + Lr) : (float2*)(s.Q + (D + 1) * L);
   }
   s.rec = carve_records<D>((char*)end, rec_cap);
   s.wsum = (int*)((char*)end + (size_t)rec_cap * FPS_REC_SLOT_BYTES(D));
@@ -315,6 +320,16 @@ __device__ __forceinline__ int bin_exponent(uint32_t amax_bits) {
 }
 __device__ __forceinline__ long long fixed_term(float v, int e) { return (long long)(int)__builtin_ldexpf(v, e); }
 __device__ __forceinline__ float fixed_value(long long v, int e) { return (float)__builtin_ldexp((double)v, -e); }
+
+// The same with 32-bit sums, when the bin's entry count n is known: e =
+// 29 - ea - en with n < 2^en keeps every term below 2^(30 - en) and the sum
+// below 2^30. Integer addition is exact and commutative, so the sums can be
+// accumulated with LDS atomics in any order (wrapping partial sums included).
+__device__ __forceinline__ int bin_exponent32(uint32_t amax_bits, int n) {
+  return bin_exponent(amax_bits) - (32 - __clz(n > 1 ? n : 1));
+}
+__device__ __forceinline__ int fixed_term32(float v, int e) { return (int)__builtin_ldexpf(v, e); }
+__device__ __forceinline__ float fixed_value32(int v, int e) { return __builtin_ldexpf((float)v, -e); }
 
 // Wave path of the solve loop (L = 64 E, 64 <= L <= 512, one wave per
 // line): wave w holds line w's values at l = lane + 64 e in registers.
@@ -369,10 +384,12 @@ __device__ __forceinline__ void wave_fft_to_lds(const float2 (&in)[kEMax], const
 // contributes a_j e^{+j 2 pi p_j^{(i)} / L} to bin b_j = [sum_k alpha_k c_k
 // m_jk]_L of line i, p_j^{(i)} = [sum_k tau_k^{(i)} c_k m_jk]_L (Eq.
 // freqSum, Eq. orthogonality). First, each set entry j = j0, j0 + js, ...
-// < n is linked into the list of its bin for this iteration's slope.
+// < n is linked into the list of its bin for this iteration's slope, the
+// bin's largest amplitude component is raised to the entry's and its entry
+// count (when kept) incremented.
 template <int D, bool kPow2, bool kRecLds>
 __device__ __forceinline__ void link_bins(const Geo<D>& g, const uint32_t (&al)[D], const RecStore& rs, int* head,
-                                          uint32_t* bmax, int j0, int js, int n) {
+                                          uint32_t* bmax, int* bcnt, int j0, int js, int n) {
   const uint32_t L = g.L;
   for (int j = j0; j < n; j += js) {
     uint32_t b = 0;
@@ -382,12 +399,48 @@ __device__ __forceinline__ void link_bins(const Geo<D>& g, const uint32_t (&al)[
     const float2 a = rs_ld<kRecLds>(rs.sa, j);
     rs_st<kRecLds>(rs.nx, j, atomicExch(&head[b], j));
     atomicMax(&bmax[b], __float_as_uint(fmaxf(fabsf(a.x), fabsf(a.y))));
+    if (bcnt) atomicAdd(&bcnt[b], 1);
   }
 }
 
-// Then the thread that owns a bin sums its list's contributions on the D+1
-// lines (fixed point at scale 2^e from the bin's largest amplitude, so the
-// sum is the same for any list order) into sum[i]. A list holds at most the n set entries, all with
+// Then every thread takes set entries j = j0, j0 + js, ... < n and adds
+// their projections on the D+1 lines to their bin's fixed-point sums in Q
+// (scale from the bin's largest amplitude and entry count; LDS integer
+// atomics, exact in any order).
+template <int D, bool kPow2, bool kRecLds>
+__device__ __forceinline__ void accumulate_bins(const Geo<D>& g, const uint32_t (&al)[D], const uint32_t (&ta)[D],
+                                                const RecStore& rs, const float2* tw, const uint32_t* bmax,
+                                                const int* bcnt, int2* Q, int j0, int js, int n) {
+  const uint32_t L = g.L;
+  for (int j = j0; j < n; j += js) {
+    uint32_t gk[D];
+    uint32_t b = 0, p0 = 0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      gk[k] = g.c[k] * (uint32_t)rs_ld<kRecLds>(rs.sf, j * D + k);
+      b = umod<kPow2>(b + al[k] * gk[k], L);
+      p0 = umod<kPow2>(p0 + ta[k] * gk[k], L);
+    }
+    const float2 a = rs_ld<kRecLds>(rs.sa, j);
+    const int e = bin_exponent32(bmax[b], bcnt[b]);
+    float2 c = c_mulc(a, tw[p0]);
+    atomicAdd(&Q[b].x, fixed_term32(c.x, e));
+    atomicAdd(&Q[b].y, fixed_term32(c.y, e));
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      uint32_t p = p0 + gk[k];
+      if (p >= L) p -= L;
+      c = c_mulc(a, tw[p]);
+      atomicAdd(&Q[(k + 1) * L + b].x, fixed_term32(c.x, e));
+      atomicAdd(&Q[(k + 1) * L + b].y, fixed_term32(c.y, e));
+    }
+  }
+}
+
+// Long lines, where LDS has no room for the per-bin sums: the thread that
+// owns a bin sums its list's contributions on the D+1 lines (fixed point at
+// scale 2^e from the bin's largest amplitude, so the sum is the same for any
+// list order) into sum[i]. A list holds at most the n set entries, all with
 // slots below n; the walk stops there whatever the links say.
 template <int D, bool kPow2, bool kRecLds>
 __device__ __forceinline__ void list_sum(const Geo<D>& g, const uint32_t (&ta)[D], const RecStore& rs,
@@ -543,7 +596,9 @@ __device__ __forceinline__ void solve_cube(const CubeDesc& cd, const float2* __r
       s.tw[e] = ld_g(twall, cd.tw_off + e);
       s.head[e] = -1;
       s.bmax[e] = 0u;
+      s.bcnt[e] = 0;
     }
+    for (uint32_t e = tid; e < (D + 1) * L; e += B) s.Q[e] = make_int2(0, 0);
   }
   const float2* tw = serial ? twall + cd.tw_off : s.tw;
   float2* oamps = (float2*)out.amps;
@@ -620,7 +675,8 @@ __device__ __forceinline__ void solve_cube(const CubeDesc& cd, const float2* __r
           wave_prefetch<D, kPow2>(pfw, E, g, x, at + 2 * D, pre + (int64_t)(t + 1) * (D + 1) * L, t + 1 < pre_count,
                                   wv);
       } else if (conc) {
-        link_bins<D, kPow2, kRecLds>(g, al, rs, s.head, s.bmax, tid - (D + 1) * 64, B - (D + 1) * 64, kc_set);
+        link_bins<D, kPow2, kRecLds>(g, al, rs, s.head, s.bmax, s.bcnt, tid - (D + 1) * 64, B - (D + 1) * 64,
+                                     kc_set);
       }
       rec_barrier<kRecLds>();
       S = s.bufA;
@@ -651,16 +707,18 @@ __device__ __forceinline__ void solve_cube(const CubeDesc& cd, const float2* __r
         // spectra (Eq. freqSum) go through an unnormalised inverse DFT, read
         // as the forward DFT at index (L - l) mod L, and are subtracted from
         // the samples (held divided by L, hence the constructed ones too).
-        link_bins<D, kPow2, kRecLds>(g, al, rs, s.head, s.bmax, tid, B, kc_set);
+        link_bins<D, kPow2, kRecLds>(g, al, rs, s.head, s.bmax, s.bcnt, tid, B, kc_set);
         rec_barrier<kRecLds>();
+        accumulate_bins<D, kPow2, kRecLds>(g, al, ta, rs, tw, s.bmax, s.bcnt, s.Q, tid, B, kc_set);
+        lds_barrier();
         for (uint32_t m = tid; m < L; m += B) {
-          float2 sum[D + 1];
-#pragma unroll
-          for (int i = 0; i <= D; ++i) sum[i] = make_float2(0.f, 0.f);
           const int h = s.head[m];
-          if (h >= 0) list_sum<D, kPow2, kRecLds>(g, ta, rs, tw, h, kc_set, bin_exponent(s.bmax[m]), sum);
+          const int e = h >= 0 ? bin_exponent32(s.bmax[m], s.bcnt[m]) : 0;
 #pragma unroll
-          for (int i = 0; i <= D; ++i) s.P[i * L + m] = sum[i];
+          for (int i = 0; i <= D; ++i) {
+            const int2 q = s.Q[i * L + m];
+            s.P[i * L + m] = h >= 0 ? make_float2(fixed_value32(q.x, e), fixed_value32(q.y, e)) : make_float2(0.f, 0.f);
+          }
         }
         lds_barrier();
         const float2* R = block_fft<kPow2>(s.P, s.bufB, D + 1, (int)L, cd.nstages, cd.radix, tw);
@@ -670,6 +728,8 @@ __device__ __forceinline__ void solve_cube(const CubeDesc& cd, const float2* __r
             s.bufA[i * L + l] = c_sub(s.bufA[i * L + l], c_scale(R[i * L + lr], inv_L));
           }
         lds_barrier();
+        // the sums (in the same buffer) start at zero next iteration
+        for (uint32_t e = tid; e < (D + 1) * L; e += B) s.Q[e] = make_int2(0, 0);
       }
       S = precomputed ? s.bufA : block_fft<kPow2>(s.bufA, s.bufB, D + 1, (int)L, cd.nstages, cd.radix, tw);
       if (use_pf && t + 1 < T)
@@ -684,8 +744,13 @@ __device__ __forceinline__ void solve_cube(const CubeDesc& cd, const float2* __r
         }
         lds_barrier();
       }
-      link_bins<D, kPow2, kRecLds>(g, al, rs, s.head, s.bmax, tid, B, kc_set);
+      link_bins<D, kPow2, kRecLds>(g, al, rs, s.head, s.bmax, serial ? nullptr : s.bcnt, tid, B, kc_set);
       rec_barrier<kRecLds>();
+    }
+    if (!serial && !literal && kc_set > 0) {
+      // all threads add the entries' projections to their bins' sums
+      accumulate_bins<D, kPow2, kRecLds>(g, al, ta, rs, tw, s.bmax, s.bcnt, s.Q, tid, B, kc_set);
+      lds_barrier();
     }
 
     // Test, decode and record, bins in ascending order: a pass covers up to
@@ -717,7 +782,16 @@ __device__ __forceinline__ void solve_cube(const CubeDesc& cd, const float2* __r
           const int h = s.head[m];
           if (h >= 0 && !literal) {
             float2 sum[D + 1];
-            list_sum<D, kPow2, kRecLds>(g, ta, rs, tw, h, kc_set, bin_exponent(s.bmax[m]), sum);
+            if (serial) {
+              list_sum<D, kPow2, kRecLds>(g, ta, rs, tw, h, kc_set, bin_exponent(s.bmax[m]), sum);
+            } else {
+              const int e = bin_exponent32(s.bmax[m], s.bcnt[m]);
+#pragma unroll
+              for (int i = 0; i <= D; ++i) {
+                const int2 q = s.Q[i * L + m];
+                sum[i] = make_float2(fixed_value32(q.x, e), fixed_value32(q.y, e));
+              }
+            }
 #pragma unroll
             for (int i = 0; i <= D; ++i) r[i] = c_sub(r[i], sum[i]);
           }
@@ -726,6 +800,11 @@ __device__ __forceinline__ void solve_cube(const CubeDesc& cd, const float2* __r
             if (cand[j]) mslot[j] = find_in_list<D, kRecLds>(rs, h, kc_set, f[j]);
             s.head[m] = -1;  // the list is rebuilt next iteration
             s.bmax[m] = 0u;
+            if (!serial) {
+              s.bcnt[m] = 0;
+#pragma unroll
+              for (int i = 0; i <= D; ++i) s.Q[i * L + m] = make_int2(0, 0);
+            }
           }
           isnew[j] = cand[j] && mslot[j] < 0;
         }
@@ -835,9 +914,9 @@ __device__ __forceinline__ void solve_cube(const CubeDesc& cd, const float2* __r
               si = rs_ld<kRecLds>(rs.sp, mslot[j]) & 0x7fffffff;
               rs_st<kRecLds>(rs.sp, mslot[j], (int32_t)((uint32_t)si | 0x80000000u));
             }
-            rs_st<kRecLds>(rs.dt, di, t);
-            rs_st<kRecLds>(rs.dm, di, (int32_t)(m0 + (uint32_t)(j * B) + tid));
-            rs_st<kRecLds>(rs.ds, di, si);
+            st_gi(out.rec_iter, di, t);
+            st_gi(out.rec_bin, di, (int32_t)(m0 + (uint32_t)(j * B) + tid));
+            st_gi(out.rec_sin, di, si);
           } else if (!isnew[j]) {
             rs_st<kRecLds>(rs.sa, mslot[j], mold[j]);
           }
@@ -872,7 +951,8 @@ __device__ __forceinline__ void solve_cube(const CubeDesc& cd, const float2* __r
   // indices; otherwise a merged frequency whose amplitude sum has |a| <=
   // theta0 is not part of the set (Eq. sigModel2: a != 0) and moves behind
   // the kept ones, both groups in first-detection order.
-  rec_barrier<kRecLds>();
+  // (a full barrier: the detection trace in the outputs is read below)
+  __syncthreads();
   if (full) {
     kc_det = max_k;
     kc_set = max(kc_set, s.cnt[2]);
@@ -934,11 +1014,9 @@ __device__ __forceinline__ void solve_cube(const CubeDesc& cd, const float2* __r
     }
     rec_barrier<kRecLds>();
   }
-  for (int i = tid; i < kc_det; i += B) {
-    st_gi(out.rec_iter, i, rs_ld<kRecLds>(rs.dt, i));
-    st_gi(out.rec_bin, i, rs_ld<kRecLds>(rs.dm, i));
-    const int si = rs_ld<kRecLds>(rs.ds, i);
-    st_gi(out.rec_sin, i, any_merge ? rs_ld<kRecLds>(rs.nx, si) : si);
+  if (any_merge) {
+    // detections point at canonical set indices: map them to output positions
+    for (int i = tid; i < kc_det; i += B) st_gi(out.rec_sin, i, rs_ld<kRecLds>(rs.nx, ld_gi(out.rec_sin, i)));
   }
   if (tid == 0) {
     st_gi(out.info, 0, kept);

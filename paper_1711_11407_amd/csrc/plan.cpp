@@ -219,6 +219,8 @@ fpssft_status hip_status(hipError_t e) {
 // order array (shortest lines first) and of the line-FFT item list.
 struct Group {
   fpssft::KernelKey key;
+  int32_t L = 0;        // line length of its cubes (one-length groups), else 0
+  int lines_threads = 0;  // line gather + FFT work-group size
   int first = 0;        // into order[]
   int count = 0;
   int item_first = 0;   // into items[]
@@ -244,7 +246,15 @@ struct fpssft_plan_st {
   std::vector<int32_t> sched;
   std::vector<float2> tw;
   std::vector<int> group_of;   // per cube
+  std::vector<int> cthreads;   // per cube: solve work-group size
+  std::vector<int> clthreads;  // per cube: line-kernel work-group size
+  std::vector<int> clsamples;  // per cube: line-kernel item size (samples)
   std::vector<Group> groups;
+  // concurrent group launches: side streams joined back to the caller's
+  static constexpr int kSide = 3;
+  hipStream_t side[kSide] = {};
+  hipEvent_t ev_fork = nullptr;
+  hipEvent_t ev_join[kSide] = {};
   int64_t spec_elems = 0;
   LaunchCtx ctx{};
   CubeDesc* d_descs = nullptr;
@@ -285,29 +295,34 @@ bool wave_eligible(const CubeDesc& c) {
 // count, and for D >= 3 at least D+3 waves, so that two waves link records
 // while the D+1 line waves transform (3-D: 117 against 126 us on a 128^3
 // cube).
-int solve_threads(const fpssft_tuning& tn, int D) {
-  return D >= 3 ? std::max(tn.block_threads, std::min(512, 64 * (D + 3))) : tn.block_threads;
+int solve_threads(int tuned, int D) {
+  return D >= 3 ? std::max(tuned, std::min(512, 64 * (D + 3))) : tuned;
 }
 
-// The one-wave-per-line solve path: an eligible line and at least D+1 waves.
-bool uses_wave_path(const fpssft_tuning& tn, const CubeDesc& c) {
-  return wave_eligible(c) && solve_threads(tn, c.D) / 64 >= c.D + 1;
+// The one-wave-per-line solve path: an eligible line and at least D+1 waves
+// in a work-group of `threads`.
+bool uses_wave_path(int threads, const CubeDesc& c) {
+  return wave_eligible(c) && threads / 64 >= c.D + 1;
 }
 
 size_t solve_lds_bytes(const CubeDesc& c, int rec_cap, bool wave) {
   // The layout of carve_solve_lds: the D+1 spectra, and on the block path a
   // second buffer (the FFT's) or, with long lines, one line of scratch that
   // also holds the bin-list words; the twiddles; the constructed spectra of
-  // the time-domain construction-subtraction; the bin-list heads and
-  // largest amplitudes (2 x L ints, each rounded to 8 bytes); per record
-  // slot the set entry and the detection; the exchange words and counters.
+  // the time-domain construction-subtraction; the bin-list heads, largest
+  // amplitudes and entry counts (3 x L ints, each rounded to 8 bytes) and
+  // the fixed-point projection sums ((D+1) L int pairs, in the constructed
+  // spectra's buffer when there is one); per record slot the set entry; the
+  // exchange words and counters.
   const size_t lines = (size_t)(c.D + 1) * c.L;
   size_t b;
   if (c.serial) {
     b = (lines + c.L) * sizeof(float2);
   } else {
     b = (lines + (wave ? 0 : lines) + c.L + ((!wave && (c.flags & FPS_LITERAL_PEEL)) ? lines : 0)) * sizeof(float2);
-    b += 2 * (size_t)((c.L + 1) & ~1) * sizeof(int);
+    b += 3 * (size_t)((c.L + 1) & ~1) * sizeof(int);
+    // the sums share the constructed spectra's buffer when there is one
+    if (wave || !(c.flags & FPS_LITERAL_PEEL)) b += lines * 2 * sizeof(int);
   }
   b += (size_t)rec_cap * FPS_REC_SLOT_BYTES(c.D);
   b += 64 * sizeof(int);
@@ -328,7 +343,7 @@ size_t lines_single_lds_bytes(const CubeDesc& c) {
 fpssft::KernelKey key_of(const fpssft_plan_t p, int c) {
   const CubeDesc& cd = p->descs[c];
   const bool pow2 = cd.Lmask >= 0;
-  return fpssft::KernelKey{cd.D, pow2, cd.rec_lds > 0, uses_wave_path(p->tune, cd)};
+  return fpssft::KernelKey{cd.D, pow2, cd.rec_lds > 0, uses_wave_path(p->cthreads[c], cd)};
 }
 
 void destroy_plan(fpssft_plan_t p) {
@@ -340,6 +355,11 @@ void destroy_plan(fpssft_plan_t p) {
   if (p->gexec) hipGraphExecDestroy(p->gexec);
   if (p->graph) hipGraphDestroy(p->graph);
   if (p->cap_stream) hipStreamDestroy(p->cap_stream);
+  for (int i = 0; i < fpssft_plan_st::kSide; ++i) {
+    if (p->side[i]) hipStreamDestroy(p->side[i]);
+    if (p->ev_join[i]) hipEventDestroy(p->ev_join[i]);
+  }
+  if (p->ev_fork) hipEventDestroy(p->ev_fork);
   p->xs_tab.release();
   p->outs_tab.release();
   p->ga_tab.release();
@@ -379,7 +399,8 @@ fpssft_status build_plan(const fpssft_desc* descs, int32_t batch, const fpssft_t
   if (v <= 2048) return FPSSFT_ERR_UNSUPPORTED;
   p->lds_max = (size_t)v - 1024;
   p->B = batch;
-  fpssft_tuning tn{256, 8, 8, 4, 256, 0, 3072};
+  fpssft_tuning tn{256, 8, 8, 4, 256, 0, 3072, 0, 0, nullptr};
+  std::vector<fpssft_shape_tuning> shapes;
   if (tuning) {
     if (tuning->block_threads) tn.block_threads = tuning->block_threads;
     if (tuning->max_radix) tn.max_radix = tuning->max_radix;
@@ -388,7 +409,19 @@ fpssft_status build_plan(const fpssft_desc* descs, int32_t batch, const fpssft_t
     if (tuning->lines_threads) tn.lines_threads = tuning->lines_threads;
     tn.direct_launch = tuning->direct_launch != 0;
     if (tuning->lines_samples) tn.lines_samples = tuning->lines_samples;
+    tn.group_by_length = tuning->group_by_length != 0;
+    if (tuning->nshapes < 0 || (tuning->nshapes > 0 && !tuning->shapes)) return FPSSFT_ERR_INVALID_ARG;
+    for (int i = 0; i < tuning->nshapes; ++i) {
+      const fpssft_shape_tuning& sh = tuning->shapes[i];
+      if (sh.ndim < 1 || sh.ndim > FPSSFT_MAX_D || sh.line_length < 1) return FPSSFT_ERR_INVALID_ARG;
+      if (sh.block_threads && (sh.block_threads < 64 || sh.block_threads > 512 || sh.block_threads % 64))
+        return FPSSFT_ERR_INVALID_ARG;
+      if (sh.lines_samples < 0) return FPSSFT_ERR_INVALID_ARG;
+      shapes.push_back(sh);
+    }
   }
+  tn.nshapes = 0;
+  tn.shapes = nullptr;
   if (tn.block_threads < 64 || tn.block_threads > 512 || tn.block_threads % 64) return FPSSFT_ERR_INVALID_ARG;
   if (tn.lines_threads < 64 || tn.lines_threads > 1024 || tn.lines_threads % 64) return FPSSFT_ERR_INVALID_ARG;
   if (tn.max_radix != 2 && tn.max_radix != 4 && tn.max_radix != 8) return FPSSFT_ERR_INVALID_ARG;
@@ -397,6 +430,9 @@ fpssft_status build_plan(const fpssft_desc* descs, int32_t batch, const fpssft_t
 
   std::map<int32_t, int32_t> tw_off;
   p->descs.resize(batch);
+  p->cthreads.assign(batch, 0);
+  p->clthreads.assign(batch, 0);
+  p->clsamples.assign(batch, 0);
   int64_t max_pre = 0;
   int64_t rec_ws_bytes = 0;
   for (int32_t c = 0; c < batch; ++c) {
@@ -422,6 +458,16 @@ fpssft_status build_plan(const fpssft_desc* descs, int32_t batch, const fpssft_t
       if (k >= d.ndim) cd.stride[k] = 0;
     }
     cd.Lmask = is_pow2(L) ? L - 1 : -1;
+    // launch shapes: the (D, L) class's tuned values over the plan-wide ones
+    int bt = tn.block_threads, ls = tn.lines_samples;
+    for (const fpssft_shape_tuning& sh : shapes) {
+      if (sh.ndim != d.ndim || sh.line_length != L) continue;
+      if (sh.block_threads) bt = sh.block_threads;
+      if (sh.lines_samples) ls = sh.lines_samples;
+    }
+    p->cthreads[c] = solve_threads(bt, d.ndim);
+    p->clthreads[c] = tn.lines_threads;
+    p->clsamples[c] = ls;
     if (!factor_fft(L, tn.max_radix, cd.radix, &cd.nstages)) return FPSSFT_ERR_UNSUPPORTED;
     cd.inv_L = (float)(1.0 / (double)L);
     cd.zero_thresh = d.zero_thresh;
@@ -457,7 +503,7 @@ fpssft_status build_plan(const fpssft_desc* descs, int32_t batch, const fpssft_t
     const int32_t pre_T = (cd.serial || (cd.flags & FPS_LITERAL_PEEL)) ? 0 : std::min(T, tn.chunk_iters);
     max_pre = std::max<int64_t>(max_pre, (int64_t)pre_T * (d.ndim + 1) * L);
     p->max_N = std::max(p->max_N, cd.N);
-    const bool wave = uses_wave_path(tn, cd);
+    const bool wave = uses_wave_path(p->cthreads[c], cd);
     if (solve_lds_bytes(cd, 0, wave) > p->lds_max || lines_single_lds_bytes(cd) > p->lds_max)
       return FPSSFT_ERR_UNSUPPORTED;
     // The record store stays in LDS when the cube's spectra and records fit;
@@ -478,12 +524,18 @@ fpssft_status build_plan(const fpssft_desc* descs, int32_t batch, const fpssft_t
   p->group_of.assign(batch, -1);
   for (int32_t c = 0; c < batch; ++c) {
     const fpssft::KernelKey k = key_of(p, c);
+    const int32_t gl = tn.group_by_length ? p->descs[c].L : 0;
     int gi = -1;
-    for (size_t i = 0; i < p->groups.size(); ++i)
-      if (p->groups[i].key == k) gi = (int)i;
+    for (size_t i = 0; i < p->groups.size(); ++i) {
+      const Group& g = p->groups[i];
+      if (g.key == k && g.L == gl && g.threads == p->cthreads[c] && g.lines_threads == p->clthreads[c]) gi = (int)i;
+    }
     if (gi < 0) {
       Group g;
       g.key = k;
+      g.L = gl;
+      g.threads = p->cthreads[c];
+      g.lines_threads = p->clthreads[c];
       p->groups.push_back(g);
       gi = (int)p->groups.size() - 1;
     }
@@ -500,7 +552,6 @@ fpssft_status build_plan(const fpssft_desc* descs, int32_t batch, const fpssft_t
   for (size_t gi = 0; gi < p->groups.size(); ++gi) {
     Group& g = p->groups[gi];
     g.first = -1;
-    g.threads = solve_threads(tn, g.key.D);
     for (int i = 0; i < batch; ++i) {
       if (p->group_of[order[i]] != (int)gi) continue;
       if (g.first < 0) g.first = i;
@@ -521,8 +572,8 @@ fpssft_status build_plan(const fpssft_desc* descs, int32_t batch, const fpssft_t
       else
         g.maxL = std::max(g.maxL, cd.L);
       // iterations per item: about lines_samples samples, else lines_wg
-      const int32_t wg = tn.lines_samples > 0 ? std::max<int32_t>(1, tn.lines_samples / ((cd.D + 1) * cd.L))
-                                              : tn.lines_wg;
+      const int32_t ls = p->clsamples[c];
+      const int32_t wg = ls > 0 ? std::max<int32_t>(1, ls / ((cd.D + 1) * cd.L)) : tn.lines_wg;
       for (int32_t t = 0; t < cd.T; t += wg) {
         LineItem li{};
         li.cube = c;
@@ -573,7 +624,7 @@ fpssft_status build_plan(const fpssft_desc* descs, int32_t batch, const fpssft_t
     g.grid = (int)std::max<int64_t>(1, std::min<int64_t>(g.count, (int64_t)occ * p->ncu));
     int locc = 0;
     HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &locc, fpssft::kernel_ptr(fpssft::KernelKind::kLines, g.key), tn.lines_threads, g.lds_lines));
+        &locc, fpssft::kernel_ptr(fpssft::KernelKind::kLines, g.key), g.lines_threads, g.lds_lines));
     if (locc < 1) return FPSSFT_ERR_UNSUPPORTED;
     const int64_t lg = std::min<int64_t>((int64_t)locc * p->ncu, ((int64_t)g.item_count + 7) / 8 * 8);
     g.lines_grid = (int)std::max<int64_t>(8, lg / 8 * 8);
@@ -609,6 +660,14 @@ fpssft_status build_plan(const fpssft_desc* descs, int32_t batch, const fpssft_t
   p->ctx.tw = p->d_tw;
   p->ctx.rec_ws = p->d_recws;
   HIP_TRY(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
+  if (p->groups.size() > 1) {
+    // default-priority side streams for the concurrent group launches
+    for (int i = 0; i < fpssft_plan_st::kSide; ++i) {
+      HIP_TRY(hipStreamCreateWithFlags(&p->side[i], hipStreamNonBlocking));
+      HIP_TRY(hipEventCreateWithFlags(&p->ev_join[i], hipEventDisableTiming));
+    }
+    HIP_TRY(hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming));
+  }
   return FPSSFT_OK;
 }
 
@@ -625,6 +684,28 @@ OutPtrs to_ptrs(const fpssft_out& o) {
   p.rec_sin = o.rec_sin;
   p.info = o.info;
   return p;
+}
+
+// Runs launch(group index, stream) for every group: on `st` when there is
+// one, else concurrently, the first on `st` and the others on the side
+// streams, forked from `st` by an event and joined back into it (inside a
+// stream capture, the side streams become parallel branches of the graph).
+template <class Launch>
+fpssft_status launch_groups(fpssft_plan_t p, hipStream_t st, Launch&& launch) {
+  const int ng = (int)p->groups.size();
+  if (ng <= 1 || !p->ev_fork) {
+    for (int gi = 0; gi < ng; ++gi) HIP_TRY(launch(gi, st));
+    return FPSSFT_OK;
+  }
+  const int nside = std::min(fpssft_plan_st::kSide, ng - 1);
+  HIP_TRY(hipEventRecord(p->ev_fork, st));
+  for (int i = 0; i < nside; ++i) HIP_TRY(hipStreamWaitEvent(p->side[i], p->ev_fork, 0));
+  for (int gi = 0; gi < ng; ++gi) HIP_TRY(launch(gi, gi == 0 ? st : p->side[(gi - 1) % fpssft_plan_st::kSide]));
+  for (int i = 0; i < nside; ++i) {
+    HIP_TRY(hipEventRecord(p->ev_join[i], p->side[i]));
+    HIP_TRY(hipStreamWaitEvent(st, p->ev_join[i], 0));
+  }
+  return FPSSFT_OK;
 }
 
 }  // namespace
@@ -724,7 +805,7 @@ fpssft_status fpssft_execute(fpssft_plan_t p, int32_t cube, const void* x, const
   const int pre = (cd.serial || (cd.flags & FPS_LITERAL_PEEL)) ? 0 : std::min(cd.T, p->tune.chunk_iters);
   if (pre > 0) {
     HIP_TRY(fpssft::launch_lines_single(p->ctx, key, cube, (const float2*)x, 0, pre, p->d_pre, cd.L,
-                                        lines_single_lds_bytes(cd), p->tune.lines_threads, st));
+                                        lines_single_lds_bytes(cd), p->clthreads[cube], st));
   }
   char* rec = cd.rec_lds ? nullptr : p->d_recws + cd.rec_off;
   HIP_TRY(fpssft::launch_solve_plain(p->ctx, key, cube, (const float2*)x, to_ptrs(*out), p->d_pre, pre, rec,
@@ -750,7 +831,7 @@ fpssft_status fpssft_execute_noalloc(fpssft_plan_t p, int32_t cube, const void* 
   const Group& g = p->groups[p->group_of[cube]];
   if (pre > 0) {
     HIP_TRY(fpssft::launch_lines_single(p->ctx, key, cube, (const float2*)x, 0, pre, pre_buf, cd.L,
-                                        lines_single_lds_bytes(cd), p->tune.lines_threads, st));
+                                        lines_single_lds_bytes(cd), p->clthreads[cube], st));
   }
   HIP_TRY(fpssft::launch_solve_plain(p->ctx, key, cube, (const float2*)x, to_ptrs(*out), pre_buf, pre, rec,
                                      g.lds_solve, g.threads, st));
@@ -769,34 +850,28 @@ fpssft_status fpssft_execute_batched(fpssft_plan_t p, const void* const* xs, con
   hipStream_t st = (hipStream_t)stream;
   HIP_TRY(p->xs_tab.update(xs, st));
   HIP_TRY(p->outs_tab.update(op.data(), st));
+  auto solve = [&](int gi, hipStream_t s) {
+    const Group& g = p->groups[gi];
+    return fpssft::launch_solve_batched(p->ctx, g.key, (const float2* const*)p->xs_tab.dev,
+                                        (const OutPtrs*)p->outs_tab.dev, p->d_order + g.first, g.count,
+                                        p->d_queue + 2 * gi, g.grid, g.lds_solve, g.threads, s);
+  };
   if (p->tune.direct_launch) {
-    // The same persistent launches straight on the stream: a graph of one
-    // kernel per instantiation saves nothing here and its launch leaves the
-    // GPU idle for several microseconds between steps.
-    for (size_t gi = 0; gi < p->groups.size(); ++gi) {
-      const Group& g = p->groups[gi];
-      HIP_TRY(fpssft::launch_solve_batched(p->ctx, g.key, (const float2* const*)p->xs_tab.dev,
-                                           (const OutPtrs*)p->outs_tab.dev, p->d_order + g.first, g.count,
-                                           p->d_queue + 2 * gi, g.grid, g.lds_solve, g.threads, st));
-    }
-    return FPSSFT_OK;
+    // The persistent launches straight on the stream (concurrent ones on
+    // side streams joined back to it): for a single launch a graph saves
+    // nothing, and its replay leaves the GPU idle for several microseconds.
+    return launch_groups(p, st, solve);
   }
   if (!p->gexec) {
-    // One graph: one persistent launch per group (each launch finds its
-    // queue counters at zero and leaves them so).
+    // One graph: one persistent launch per group, as parallel branches
+    // (each launch finds its queue counters at zero and leaves them so).
     HIP_TRY(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
-    hipError_t e = hipSuccess;
-    for (size_t gi = 0; e == hipSuccess && gi < p->groups.size(); ++gi) {
-      const Group& g = p->groups[gi];
-      e = fpssft::launch_solve_batched(p->ctx, g.key, (const float2* const*)p->xs_tab.dev,
-                                       (const OutPtrs*)p->outs_tab.dev, p->d_order + g.first, g.count,
-                                       p->d_queue + 2 * gi, g.grid, g.lds_solve, g.threads, p->cap_stream);
-    }
+    const fpssft_status r = launch_groups(p, p->cap_stream, solve);
     hipGraph_t graph = nullptr;
     hipError_t e2 = hipStreamEndCapture(p->cap_stream, &graph);
-    if (e != hipSuccess) {
+    if (r != FPSSFT_OK) {
       if (graph) hipGraphDestroy(graph);
-      return hip_status(e);
+      return r;
     }
     if (e2 != hipSuccess) return hip_status(e2);
     p->graph = graph;
@@ -814,7 +889,7 @@ fpssft_status fpssft_lines_fft(fpssft_plan_t p, int32_t cube, const void* x, int
   if (t0 < 0 || count < 0 || (int64_t)t0 + count > cd.T) return FPSSFT_ERR_INVALID_ARG;
   if (count == 0) return FPSSFT_OK;
   HIP_TRY(fpssft::launch_lines_single(p->ctx, key_of(p, cube), cube, (const float2*)x, t0, count,
-                                      (float2*)spectra, cd.L, lines_single_lds_bytes(cd), p->tune.lines_threads,
+                                      (float2*)spectra, cd.L, lines_single_lds_bytes(cd), p->clthreads[cube],
                                       (hipStream_t)stream));
   return FPSSFT_OK;
 }
@@ -827,14 +902,13 @@ fpssft_status fpssft_lines_fft_all(fpssft_plan_t p, const void* const* xs, void*
   hipStream_t st = (hipStream_t)stream;
   HIP_TRY(p->xs_tab.update(xs, st));
   HIP_TRY(fpssft::launch_reset(p->d_lqueue, 8 * (int)p->groups.size(), st));
-  for (size_t gi = 0; gi < p->groups.size(); ++gi) {
+  return launch_groups(p, st, [&](int gi, hipStream_t s) {
     const Group& g = p->groups[gi];
-    if (g.item_count == 0) continue;
-    HIP_TRY(fpssft::launch_lines_items(p->ctx, g.key, p->d_items + g.item_first, p->d_ranges + 16 * gi,
-                                       p->d_lqueue + 8 * gi, g.lines_grid, (const float2* const*)p->xs_tab.dev,
-                                       (float2*)spectra, g.maxL, g.lds_lines, p->tune.lines_threads, st));
-  }
-  return FPSSFT_OK;
+    if (g.item_count == 0) return hipSuccess;
+    return fpssft::launch_lines_items(p->ctx, g.key, p->d_items + g.item_first, p->d_ranges + 16 * gi,
+                                      p->d_lqueue + 8 * gi, g.lines_grid, (const float2* const*)p->xs_tab.dev,
+                                      (float2*)spectra, g.maxL, g.lds_lines, g.lines_threads, s);
+  });
 }
 
 fpssft_status fpssft_amp_backward(fpssft_plan_t p, int32_t cube, const fpssft_out* fwd, const void* grad_amps,

@@ -55,10 +55,9 @@ struct OutPtrs {
   int32_t* info;
 };
 
-// Bytes of one slot of a cube's record store (set entry + detection):
-// amplitude, D frequency indices, canonical set index, bin-list link,
-// detection iteration, bin and set index.
-#define FPS_REC_SLOT_BYTES(D) (8 + 4 * (D) + 5 * 4)
+// Bytes of one slot of a cube's record store (a set entry): amplitude, D
+// frequency indices, canonical set index, bin-list link.
+#define FPS_REC_SLOT_BYTES(D) (8 + 4 * (D) + 2 * 4)
 
 // One work item of the line gather + FFT kernel: `count` iterations of one
 // cube starting at t0, written at element offset `out_off`.

@@ -141,12 +141,48 @@ def test_redetection_merged_like_the_oracle(F):
         assert np.abs(got_b["dropped_amps"]).max() <= specs[0].zero_thresh
 
 
+SHAPES = [dict(ndim=2, line_length=64, block_threads=192), dict(ndim=2, line_length=128, block_threads=320),
+          dict(ndim=2, line_length=512, block_threads=512, lines_samples=1536)]
+
+
 @pytest.mark.parametrize("tuning", [dict(block_threads=128), dict(block_threads=512, max_radix=4),
-                                    dict(direct_launch=1), dict(direct_launch=0)])
+                                    dict(direct_launch=1), dict(direct_launch=0),
+                                    dict(group_by_length=1, direct_launch=1),
+                                    dict(group_by_length=1, direct_launch=0),
+                                    dict(shapes=SHAPES, direct_launch=1),
+                                    dict(shapes=SHAPES, group_by_length=1, direct_launch=0)])
 def test_batched_launch_shapes_agree(F, tuning):
+    """Every launch shape, grouping and launch form gives the oracle's
+    records, and (construction-subtraction sums being exact) the same bits
+    as the default shapes whenever the FFT radices agree."""
     cubes = W.cfg4(B=40, seed=9)
     plan, specs, xs = batched_setup(F, cubes, tuning=tuning)
     outs = plan.execute_batched(xs)
+    outs = plan.execute_batched(xs, outs)
     for c in range(0, 40, 5):
         ref, _, _ = oracle_for(plan, c, cubes[c].x, specs[c])
         compare(outs[c].host(), ref, f"{tuning} cube {c}")
+    if tuning.get("block_threads", 256) < 192:
+        return  # fewer waves than lines: the block FFT path, other rounding
+    base, _, _ = batched_setup(F, cubes)
+    bouts = base.execute_batched(xs)
+    for c in range(40):
+        a, b = outs[c].host(), bouts[c].host()
+        for key in ("freqs", "rec_iter", "rec_bin", "rec_sin"):
+            np.testing.assert_array_equal(a[key], b[key], err_msg=f"{tuning} cube {c} {key}")
+        np.testing.assert_array_equal(a["amps"], b["amps"], err_msg=f"{tuning} cube {c} amps")
+
+
+def test_grouped_line_fft_equals_single(F):
+    """The whole-budget line FFT with one concurrent launch per line length
+    and per-(D, L) item sizes equals the per-cube line FFT."""
+    torch, dev = torch_dev()
+    cubes = W.cfg4(B=24, seed=10)
+    plan, specs, xs = batched_setup(F, cubes, tuning=dict(shapes=SHAPES, group_by_length=1))
+    spec_all = plan.lines_fft_all(xs)
+    torch.cuda.synchronize()
+    for c in range(len(cubes)):
+        L, T, off = plan.info[c]
+        one = plan.lines_fft(c, xs[c], 0, T).cpu().numpy().reshape(-1)
+        blk = spec_all[off:off + T * 3 * L].cpu().numpy()
+        np.testing.assert_array_equal(blk, one, err_msg=f"cube {c}")
