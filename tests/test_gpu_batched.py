@@ -84,10 +84,13 @@ def bench_tuning():
 def test_cfg4_full_batch_parity(F):
     """The full 1024-cube workload in the launch shape the benchmark times:
     every cube against the FP64 oracle (records, trace, outcome, amplitudes
-    per record), and batched equal to plain bit for bit."""
+    per record), and batched equal to plain (bit for bit unless the plain
+    path transforms its first iterations ahead with the line kernel)."""
     log("generating cfg4 (1024 cubes)")
     cubes = W.cfg4()
-    plan, specs, xs = batched_setup(F, cubes, tuning=bench_tuning())
+    tuning = bench_tuning()
+    pre_chunk = (tuning or {}).get("chunk_iters", 8) > 0
+    plan, specs, xs = batched_setup(F, cubes, tuning=tuning)
     torch, dev = torch_dev()
     log("oracle over 1024 cubes (process pool)")
     refs = oracle_pool([("cfg4", c, plan.max_iters(c), 512, False) for c in range(len(cubes))])
@@ -108,8 +111,14 @@ def test_cfg4_full_batch_parity(F):
         compare(b, ref, f"cfg4 cube {c} {cubes[c].dims} batched")
         for key in ("k", "n", "kd", "iters", "status"):
             assert b[key] == p[key], (c, key)
-        for key in ("freqs", "amps", "rec_iter", "rec_bin", "rec_sin", "dropped_freqs"):
+        for key in ("freqs", "rec_iter", "rec_bin", "rec_sin", "dropped_freqs"):
             np.testing.assert_array_equal(b[key], p[key], err_msg=f"cube {c} {key}")
+        if pre_chunk:
+            # the plain path's first iterations come from the block FFT of
+            # the line kernel: other rounding of the same spectra
+            np.testing.assert_allclose(b["amps"], p["amps"], rtol=1e-5, atol=0, err_msg=f"cube {c}")
+        else:
+            np.testing.assert_array_equal(b["amps"], p["amps"], err_msg=f"cube {c} amps")
         worst = max(worst, max_record_error(b, ref))
         n_ok += ref.status == O.STATUS_OK
         n_merged += ref.n != ref.k
