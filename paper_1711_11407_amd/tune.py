@@ -217,7 +217,8 @@ def tune(specs, xs, reps: int = 10, plain_cubes: int = 128, log=print) -> dict:
         pref = pref or dec
         results["plain"].append(dict(chunk_iters=ch, ms=round(ms, 4), same_decisions=ok))
         log(f"plain chunk_iters={ch}: {ms * 1e3:.1f} us for {len(sub)} cubes{'' if ok else ' (rejected)'}")
-        if ok and (best_ms is None or ms < best_ms):
+        # transforming ahead costs one more launch per call: it must win by 2%
+        if ok and (best_ms is None or ms < 0.98 * best_ms):
             best_ms, best["chunk_iters"] = ms, ch
         del plan, bound
     return dict(tuning=best, results=results)
