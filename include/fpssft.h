@@ -57,7 +57,7 @@ typedef enum {
  *               [N_0] x ... x [N_{D-1}]). L = LCM(N_k) (Lemma 1).
  *  max_iters    T_max; 0 selects floor(N / ((D+1) L)) but at least 1, the
  *               paper's budget of about 100% of the samples (Sec. 3).
- *  max_k        capacity of the record list (>= 1).
+ *  max_k        capacity of the record list, 1 .. 2^26.
  *  seed         seed of the SplitMix64 line schedule (below).
  *  zero_thresh  theta0: a bin is nonzero iff |r| > theta0 (Sec. 2.2: a
  *               nonzero bin is 1-sparse with high probability).
@@ -243,9 +243,10 @@ fpssft_status fpssft_schedule_generate(const fpssft_desc* desc, int32_t T,
  * LDS (160 KB) are transformed one line at a time, with the twiddles read
  * from device memory; UNSUPPORTED when even the D+1 spectra plus one line of
  * scratch do not fit ((D+2) L * 8 bytes > 160 KB, e.g. L > 6800 for D = 2).
- * A cube's record store (max_k slots of 16 + 4 D bytes, one per set entry)
- * stays in LDS when it fits beside the spectra, else the plan allocates it
- * in device memory. */
+ * A cube's record store (max_k slots of 16 + 4 D bytes, one per set entry,
+ * and a hash of the set's frequencies, 4 bytes a slot for the smallest
+ * power of two of at least 2 max_k and 64 slots) stays in LDS when it fits
+ * beside the spectra, else the plan allocates it in device memory. */
 fpssft_status fpssft_plan_create(const fpssft_desc* descs, int32_t batch,
                                  const fpssft_tuning* tuning, fpssft_plan_t* plan);
 
@@ -306,8 +307,8 @@ fpssft_status fpssft_execute(fpssft_plan_t plan, int32_t cube, const void* x,
  * a GPU shares that GPU's array: calls that overlap on one GPU (concurrent
  * streams, other threads) race and must be ordered by the caller. Nothing in
  * the array needs to start at zero. UNSUPPORTED when the cube needs more
- * than 4 MiB: chunk_iters (D+1) L * 8 bytes rounded up to 256, plus max_k
- * (16 + 4 D) bytes when the records exceed LDS. Argument errors as for
+ * than 4 MiB: chunk_iters (D+1) L * 8 bytes rounded up to 256, plus the
+ * record store (above) when it exceeds LDS. Argument errors as for
  * fpssft_execute. */
 fpssft_status fpssft_execute_noalloc(fpssft_plan_t plan, int32_t cube, const void* x,
                                      const fpssft_out* out, void* stream);

@@ -194,9 +194,13 @@ struct RecStore {
   int32_t* sf;  // [cap][D] its frequency indices
   int32_t* sp;  // [cap] its canonical set index; the sign bit marks a
                 // frequency detected more than once
-  int32_t* nx;  // [cap] next entry projecting onto the same bin in this
-                // iteration (-1 ends a list); at the end of the cube, the
-                // slot, then the output position, of each canonical index
+  int32_t* nx;  // [cap] long lines: next entry projecting onto the same
+                // bin in this iteration (-1 ends a list); at the end of the
+                // cube, the slot, then the output position, of each
+                // canonical index
+  int32_t* ht;  // [hash slots] slot of each set frequency, -1: empty
+  uint32_t hmask;  // hash slots - 1
+  int hshift;      // 32 - log2(hash slots)
 };
 
 template <int D>
@@ -206,6 +210,10 @@ __device__ __forceinline__ RecStore carve_records(char* base, int cap) {
   r.sf = (int32_t*)(r.sa + cap);
   r.sp = r.sf + cap * D;
   r.nx = r.sp + cap;
+  r.ht = r.nx + cap;
+  const int hs = fps_rec_hash_slots(cap);
+  r.hmask = (uint32_t)hs - 1u;
+  r.hshift = __clz(hs) + 1;
   return r;
 }
 
@@ -247,11 +255,11 @@ struct SolveLds {
   float2* P;     // [(D+1) L] constructed spectra (time-domain
                  // construction-subtraction only)
   float2* tw;    // [L] twiddles W_L^k (long lines: none, read from memory)
-  int* head;     // [L] first set entry of each bin's list (long lines: in
-                 // the scratch line, once the transforms are done)
-  uint32_t* bmax;  // [L] largest amplitude component of each bin's list
-                   // (float bits; next to the heads)
-  int* bcnt;     // [L] entries in each bin's list (not with long lines)
+  int* head;     // long lines: [L] first set entry of each bin's list, in
+                 // the scratch line once the transforms are done
+  uint32_t* bmax;  // [L] largest amplitude component of the set entries
+                   // projecting onto each bin (float bits)
+  int* bcnt;     // [L] number of those entries (not with long lines)
   int2* Q;       // [(D+1) L] each bin's projection sums per line, fixed point
                  // (not with long lines)
   RecStore rec;  // the record store when it is in LDS
@@ -263,9 +271,9 @@ struct SolveLds {
 // Layout (the host's solve_lds_bytes mirrors it): the wave path keeps the
 // D+1 spectra (each wave's transform writes its row), the block path two
 // line buffers; then the twiddles, the constructed spectra of the
-// time-domain construction-subtraction, the per-bin words (list heads,
-// largest amplitudes, entry counts) and fixed-point projection sums, the
-// records and the exchange words.
+// time-domain construction-subtraction, the per-bin words (largest
+// amplitudes, entry counts) and fixed-point projection sums, the records
+// with their frequency hash and the exchange words.
 template <int D, bool kWave>
 __device__ __forceinline__ SolveLds carve_solve_lds(char* smem, int L, int rec_cap, bool serial, bool literal) {
   SolveLds s;
@@ -294,8 +302,8 @@ __device__ __forceinline__ SolveLds carve_solve_lds(char* smem, int L, int rec_c
       end += (D + 1) * L;
     }
     const int Lr = (L + 1) & ~1;
-    s.head = (int*)end;
-    s.bmax = (uint32_t*)(s.head + Lr);
+    s.head = nullptr;
+    s.bmax = (uint32_t*)end;
     s.bcnt = (int*)(s.bmax + Lr);
     // the time-domain construction-subtraction converts the sums into its
     // constructed spectra in place
@@ -303,7 +311,7 @@ __device__ __forceinline__ SolveLds carve_solve_lds(char* smem, int L, int rec_c
     end = s.P ? (float2*)(s.bcnt + Lr) : (float2*)(s.Q + (D + 1) * L);
   }
   s.rec = carve_records<D>((char*)end, rec_cap);
-  s.wsum = (int*)((char*)end + (size_t)rec_cap * FPS_REC_SLOT_BYTES(D));
+  s.wsum = (int*)((char*)end + fps_rec_bytes(D, rec_cap));
   s.cnt = s.wsum + 32;
   return s;
 }
@@ -380,26 +388,98 @@ __device__ __forceinline__ void wave_fft_to_lds(const float2 (&in)[kEMax], const
   wave_fft_lanes<E>(v, tw, [&](int k, float2 val) { dst[k] = val; });
 }
 
+// The set's frequency hash: key = the frequency's flat index, slot = its
+// record slot. The entries an iteration opens enter it while the next
+// iteration links the set, before the barrier that precedes that
+// iteration's lookups; an iteration never looks up a frequency it opened
+// itself (a frequency projects onto one bin, the one that found it). Slots
+// are never emptied during a cube, so a lookup that meets an empty slot has
+// seen every entry of its probe sequence.
+template <int D>
+__device__ __forceinline__ uint32_t freq_key(const Geo<D>& g, const int (&f)[D]) {
+  uint32_t key = 0;
+#pragma unroll
+  for (int k = 0; k < D; ++k) key += (uint32_t)f[k] * (uint32_t)g.stride[k];
+  return key;
+}
+__device__ __forceinline__ uint32_t hash_home(const RecStore& rs, uint32_t key) {
+  return (key * 0x9E3779B1u) >> rs.hshift;
+}
+template <int D, bool kRecLds>
+__device__ __forceinline__ int hash_find(const RecStore& rs, uint32_t key, const int (&f)[D]) {
+  uint32_t h = hash_home(rs, key);
+  for (uint32_t steps = 0; steps <= rs.hmask; ++steps) {
+    const int j = rs_ld<kRecLds>(rs.ht, (int)h);
+    if (j < 0) return -1;
+    bool eq = true;
+#pragma unroll
+    for (int k = 0; k < D; ++k) eq = eq && rs_ld<kRecLds>(rs.sf, j * D + k) == f[k];
+    if (eq) return j;
+    h = (h + 1u) & rs.hmask;
+  }
+  return -1;
+}
+// Entries j = j0, j0 + js, ... of [from, n) enter the hash.
+template <int D, bool kRecLds>
+__device__ __forceinline__ void hash_insert(const Geo<D>& g, const RecStore& rs, int from, int j0, int js, int n) {
+  for (int j = from + j0; j < n; j += js) {
+    int f[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) f[k] = rs_ld<kRecLds>(rs.sf, j * D + k);
+    uint32_t h = hash_home(rs, freq_key<D>(g, f));
+    for (uint32_t steps = 0; steps <= rs.hmask; ++steps) {
+      if (atomicCAS(&rs.ht[h], -1, j) == -1) break;
+      h = (h + 1u) & rs.hmask;
+    }
+  }
+}
+
 // Construction-subtraction (Sec. 2.2): the recovered sinusoid (m_j, a_j)
 // contributes a_j e^{+j 2 pi p_j^{(i)} / L} to bin b_j = [sum_k alpha_k c_k
 // m_jk]_L of line i, p_j^{(i)} = [sum_k tau_k^{(i)} c_k m_jk]_L (Eq.
-// freqSum, Eq. orthogonality). First, each set entry j = j0, j0 + js, ...
-// < n is linked into the list of its bin for this iteration's slope, the
-// bin's largest amplitude component is raised to the entry's and its entry
-// count (when kept) incremented.
+// freqSum, Eq. orthogonality). First, for each set entry j = j0, j0 + js,
+// ... < n, its bin's largest amplitude component is raised to the entry's
+// and the bin's entry count incremented; with long lines (no counts) the
+// entry is linked into its bin's list instead. The same threads enter the
+// entries of slots hfrom .. n-1 into the frequency hash.
+template <int D, bool kPow2, bool kRecLds>
+__device__ __forceinline__ uint32_t entry_bin(const Geo<D>& g, const uint32_t (&al)[D], const RecStore& rs, int j) {
+  uint32_t b = 0;
+#pragma unroll
+  for (int k = 0; k < D; ++k) b = umod<kPow2>(b + al[k] * (g.c[k] * (uint32_t)rs_ld<kRecLds>(rs.sf, j * D + k)), g.L);
+  return b;
+}
+__device__ __forceinline__ uint32_t amp_bits(float2 a) { return __float_as_uint(fmaxf(fabsf(a.x), fabsf(a.y))); }
+
 template <int D, bool kPow2, bool kRecLds>
 __device__ __forceinline__ void link_bins(const Geo<D>& g, const uint32_t (&al)[D], const RecStore& rs, int* head,
-                                          uint32_t* bmax, int* bcnt, int j0, int js, int n) {
-  const uint32_t L = g.L;
+                                          uint32_t* bmax, int* bcnt, int j0, int js, int n, int hfrom) {
+  // the entries the last iteration opened (slots hfrom .. n-1)
+  hash_insert<D, kRecLds>(g, rs, hfrom, j0, js, n);
+  if (bcnt) {
+    // two entries per step, so that their loads overlap
+    int j = j0;
+    for (; j + js < n; j += 2 * js) {
+      const uint32_t b0 = entry_bin<D, kPow2, kRecLds>(g, al, rs, j);
+      const uint32_t b1 = entry_bin<D, kPow2, kRecLds>(g, al, rs, j + js);
+      const float2 a0 = rs_ld<kRecLds>(rs.sa, j);
+      const float2 a1 = rs_ld<kRecLds>(rs.sa, j + js);
+      atomicMax(&bmax[b0], amp_bits(a0));
+      atomicAdd(&bcnt[b0], 1);
+      atomicMax(&bmax[b1], amp_bits(a1));
+      atomicAdd(&bcnt[b1], 1);
+    }
+    if (j < n) {
+      const uint32_t b = entry_bin<D, kPow2, kRecLds>(g, al, rs, j);
+      atomicMax(&bmax[b], amp_bits(rs_ld<kRecLds>(rs.sa, j)));
+      atomicAdd(&bcnt[b], 1);
+    }
+    return;
+  }
   for (int j = j0; j < n; j += js) {
-    uint32_t b = 0;
-#pragma unroll
-    for (int k = 0; k < D; ++k)
-      b = umod<kPow2>(b + al[k] * (g.c[k] * (uint32_t)rs_ld<kRecLds>(rs.sf, j * D + k)), L);
-    const float2 a = rs_ld<kRecLds>(rs.sa, j);
+    const uint32_t b = entry_bin<D, kPow2, kRecLds>(g, al, rs, j);
     rs_st<kRecLds>(rs.nx, j, atomicExch(&head[b], j));
-    atomicMax(&bmax[b], __float_as_uint(fmaxf(fabsf(a.x), fabsf(a.y))));
-    if (bcnt) atomicAdd(&bcnt[b], 1);
+    atomicMax(&bmax[b], amp_bits(rs_ld<kRecLds>(rs.sa, j)));
   }
 }
 
@@ -476,19 +556,6 @@ __device__ __forceinline__ void list_sum(const Geo<D>& g, const uint32_t (&ta)[D
   for (int i = 0; i <= D; ++i) sum[i] = make_float2(fixed_value(sr[i], e), fixed_value(si[i], e));
 }
 
-// The set entry with frequency f in the list starting at h, or -1. A
-// frequency is in at most one list per iteration (the bin it projects onto).
-template <int D, bool kRecLds>
-__device__ __forceinline__ int find_in_list(const RecStore& rs, int h, int n, const int (&f)[D]) {
-  for (int j = h, steps = 0; (unsigned)j < (unsigned)n && steps < n; j = rs_ld<kRecLds>(rs.nx, j), ++steps) {
-    bool eq = true;
-#pragma unroll
-    for (int k = 0; k < D; ++k) eq = eq && rs_ld<kRecLds>(rs.sf, j * D + k) == f[k];
-    if (eq) return j;
-  }
-  return -1;
-}
-
 // Bin m of one iteration (r: its value on lines 0..D after the peel): the
 // nonzero and magnitude-equality tests (Sec. 2.1), the phase decode of the
 // frequency (Eq. decoding) with the on-grid check, the projection-consistency
@@ -553,19 +620,22 @@ __device__ __forceinline__ bool decode_bin(const Geo<D>& g, const uint32_t (&al)
 // One cube in one work-group, iteration by iteration (Sec. 2.2).
 //
 // One iteration (wave path, more waves than lines): waves 0..D transform
-// their line into bufA while the remaining waves link the set entries into
-// per-bin lists; one barrier; the owner of each bin subtracts its list's
-// contributions from the spectra (construction-subtraction) and tests and
-// decodes the bin (Eq. decoding); one barrier per pass of bins exchanges
-// the per-wave counts of detections and new frequencies and the nonzero
-// flags. Other configurations link the entries after the transform, with
-// a barrier on each side.
+// their line into bufA while the remaining waves count the set entries per
+// bin (largest amplitude component and number, which fix the bin's
+// fixed-point scale); one barrier; every thread adds entries' projections
+// to their bins' sums; one barrier; the owner of each bin subtracts the
+// sums from the spectra (construction-subtraction) and tests and decodes
+// the bin (Eq. decoding); one barrier per pass of bins exchanges the
+// per-wave counts of detections and new frequencies and the nonzero flags.
+// Other configurations count the entries after the transform, with a
+// barrier on each side; long lines link them into per-bin lists that the
+// bin's owner sums.
 //
-// A detection whose frequency is already in the set (found in that bin's
-// list) adds its amplitude to that entry; otherwise it opens a new entry.
-// The lists give each bin exactly the entries that project onto it, so the
-// subtraction is the same as summing every detection (the set amplitudes
-// are sums of detections).
+// A detection whose frequency is already in the set (found through the
+// set's frequency hash) adds its amplitude to that entry; otherwise it
+// opens a new entry. Every entry contributes to the one bin it projects
+// onto, so the subtraction is the same as summing every detection (the set
+// amplitudes are sums of detections).
 template <int D, bool kPow2, bool kRecLds, bool kWave>
 __device__ __forceinline__ void solve_cube(const CubeDesc& cd, const float2* __restrict__ x, const OutPtrs out,
                                            const int32_t* __restrict__ sched, const float2* __restrict__ twall,
@@ -591,10 +661,10 @@ __device__ __forceinline__ void solve_cube(const CubeDesc& cd, const float2* __r
   const bool avg = (cd.flags & FPS_AMP_AVERAGE) != 0;
   SolveLds s = carve_solve_lds<D, kWave>(smem, (int)L, kRecLds ? cd.rec_lds : 0, serial, literal);
   const RecStore rs = kRecLds ? s.rec : carve_records<D>(rec_store, max_k);
+  for (uint32_t e = tid; e <= rs.hmask; e += B) rs_st<kRecLds>(rs.ht, (int)e, -1);
   if (!serial) {
     for (uint32_t e = tid; e < L; e += B) {
       s.tw[e] = ld_g(twall, cd.tw_off + e);
-      s.head[e] = -1;
       s.bmax[e] = 0u;
       s.bcnt[e] = 0;
     }
@@ -627,6 +697,7 @@ __device__ __forceinline__ void solve_cube(const CubeDesc& cd, const float2* __r
 
   int kc_det = 0;   // detections recorded (the capacity counts these)
   int kc_set = 0;   // distinct frequencies recorded
+  int kc_hash = 0;  // of which in the frequency hash (or entering it)
   bool any_merge = false;
   int xpar = 0;
   int status = kStatusIncomplete;
@@ -634,6 +705,9 @@ __device__ __forceinline__ void solve_cube(const CubeDesc& cd, const float2* __r
   bool full = false;
   for (int t = 0; t < T; ++t) {
     const int32_t* at = sch + t * 2 * D;
+    // the entries of slots hfrom .. kc_set-1 enter the hash while linking
+    const int hfrom = kc_hash;
+    kc_hash = kc_set;
     const bool precomputed = t < pre_count;
     uint32_t al[D], ta[D];
 #pragma unroll
@@ -676,7 +750,7 @@ __device__ __forceinline__ void solve_cube(const CubeDesc& cd, const float2* __r
                                   wv);
       } else if (conc) {
         link_bins<D, kPow2, kRecLds>(g, al, rs, s.head, s.bmax, s.bcnt, tid - (D + 1) * 64, B - (D + 1) * 64,
-                                     kc_set);
+                                     kc_set, hfrom);
       }
       rec_barrier<kRecLds>();
       S = s.bufA;
@@ -707,17 +781,17 @@ __device__ __forceinline__ void solve_cube(const CubeDesc& cd, const float2* __r
         // spectra (Eq. freqSum) go through an unnormalised inverse DFT, read
         // as the forward DFT at index (L - l) mod L, and are subtracted from
         // the samples (held divided by L, hence the constructed ones too).
-        link_bins<D, kPow2, kRecLds>(g, al, rs, s.head, s.bmax, s.bcnt, tid, B, kc_set);
+        link_bins<D, kPow2, kRecLds>(g, al, rs, s.head, s.bmax, s.bcnt, tid, B, kc_set, hfrom);
         rec_barrier<kRecLds>();
         accumulate_bins<D, kPow2, kRecLds>(g, al, ta, rs, tw, s.bmax, s.bcnt, s.Q, tid, B, kc_set);
         lds_barrier();
         for (uint32_t m = tid; m < L; m += B) {
-          const int h = s.head[m];
-          const int e = h >= 0 ? bin_exponent32(s.bmax[m], s.bcnt[m]) : 0;
+          const int n = s.bcnt[m];
+          const int e = n > 0 ? bin_exponent32(s.bmax[m], n) : 0;
 #pragma unroll
           for (int i = 0; i <= D; ++i) {
             const int2 q = s.Q[i * L + m];
-            s.P[i * L + m] = h >= 0 ? make_float2(fixed_value32(q.x, e), fixed_value32(q.y, e)) : make_float2(0.f, 0.f);
+            s.P[i * L + m] = n > 0 ? make_float2(fixed_value32(q.x, e), fixed_value32(q.y, e)) : make_float2(0.f, 0.f);
           }
         }
         lds_barrier();
@@ -744,7 +818,7 @@ __device__ __forceinline__ void solve_cube(const CubeDesc& cd, const float2* __r
         }
         lds_barrier();
       }
-      link_bins<D, kPow2, kRecLds>(g, al, rs, s.head, s.bmax, serial ? nullptr : s.bcnt, tid, B, kc_set);
+      link_bins<D, kPow2, kRecLds>(g, al, rs, s.head, s.bmax, serial ? nullptr : s.bcnt, tid, B, kc_set, hfrom);
       rec_barrier<kRecLds>();
     }
     if (!serial && !literal && kc_set > 0) {
@@ -779,8 +853,10 @@ __device__ __forceinline__ void solve_cube(const CubeDesc& cd, const float2* __r
           float2 r[D + 1];
 #pragma unroll
           for (int i = 0; i <= D; ++i) r[i] = S[i * L + m];
-          const int h = s.head[m];
-          if (h >= 0 && !literal) {
+          // entries of the set project onto this bin
+          const int h = serial ? s.head[m] : -1;
+          const bool has = serial ? h >= 0 : s.bcnt[m] > 0;
+          if (has && !literal) {
             float2 sum[D + 1];
             if (serial) {
               list_sum<D, kPow2, kRecLds>(g, ta, rs, tw, h, kc_set, bin_exponent(s.bmax[m]), sum);
@@ -796,9 +872,10 @@ __device__ __forceinline__ void solve_cube(const CubeDesc& cd, const float2* __r
             for (int i = 0; i <= D; ++i) r[i] = c_sub(r[i], sum[i]);
           }
           cand[j] = decode_bin<D, kPow2>(g, al, ta, r, m, th0, rho, gtol, tw, avg, nonzero, f[j], amp[j]);
-          if (h >= 0) {
-            if (cand[j]) mslot[j] = find_in_list<D, kRecLds>(rs, h, kc_set, f[j]);
-            s.head[m] = -1;  // the list is rebuilt next iteration
+          if (has) {
+            // a frequency already in the set projects onto this bin
+            if (cand[j]) mslot[j] = hash_find<D, kRecLds>(rs, freq_key<D>(g, f[j]), f[j]);
+            if (serial) s.head[m] = -1;  // the list is rebuilt next iteration
             s.bmax[m] = 0u;
             if (!serial) {
               s.bcnt[m] = 0;
@@ -1042,12 +1119,13 @@ __global__ FPS_SOLVE_ATTRS void k_solve_plain(const CubeDesc* __restrict__ descs
   solve_cube<D, kPow2, kRecLds, kWave>(descs[cube], x, out, sched, tw, pre, pre_count, lds_solve, rec_store);
 }
 
-// Persistent: every work-group loops taking the next cube of `order` from
-// the queue counter queue[0]; it leaves when the counter passes the cube
-// count, so every wave reaches the exit. Leaving, it counts itself in
-// queue[1]; the last work-group out (every other one has made its final
-// take) sets both counters back to zero for the next launch, so no reset
-// kernel precedes the launch.
+// Persistent: work-group b first solves cube order[b] (the grid is at most
+// the cube count), so the launch's first takes wait on no atomic at one
+// address; then it loops taking order[gridDim.x + queue[0]++] and leaves
+// when that index passes the cube count, so every wave reaches the exit.
+// Leaving, it counts itself in queue[1]; the last work-group out (every
+// other one has made its final take) sets both counters back to zero for
+// the next launch, so no reset kernel precedes the launch.
 template <int D, bool kPow2, bool kRecLds, bool kWave>
 __global__ FPS_SOLVE_ATTRS void k_solve_batched(const CubeDesc* __restrict__ descs, const float2* const* __restrict__ xs,
                                                 const OutPtrs* __restrict__ outs, const int32_t* __restrict__ sched,
@@ -1055,12 +1133,15 @@ __global__ FPS_SOLVE_ATTRS void k_solve_batched(const CubeDesc* __restrict__ des
                                                 int ncubes, int* __restrict__ queue, char* recws) {
   extern __shared__ __attribute__((aligned(16))) char lds_solve[];
   __shared__ int s_idx;
-  for (;;) {
-    if (threadIdx.x == 0) s_idx = atomicAdd(queue, 1);
-    __syncthreads();
-    // uniform across the work-group: keep it in a scalar register
-    const int idx = __builtin_amdgcn_readfirstlane(s_idx);
-    __syncthreads();
+  int idx = (int)blockIdx.x;
+  for (;; idx = -1) {
+    if (idx < 0) {
+      if (threadIdx.x == 0) s_idx = (int)gridDim.x + atomicAdd(queue, 1);
+      __syncthreads();
+      // uniform across the work-group: keep it in a scalar register
+      idx = __builtin_amdgcn_readfirstlane(s_idx);
+      __syncthreads();
+    }
     if (idx >= ncubes) {
       if (threadIdx.x == 0 && atomicAdd(queue + 1, 1) == (int)gridDim.x - 1) {
         atomicExch(queue, 0);

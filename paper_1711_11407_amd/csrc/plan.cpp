@@ -73,7 +73,7 @@ fpssft_status validate(const fpssft_desc* d, int32_t* L_out, int32_t* T_out) {
     N *= d->dims[k];
     if (N >= (int64_t(1) << 40)) return FPSSFT_ERR_UNSUPPORTED;
   }
-  if (d->max_k < 1 || d->max_iters < 0) return FPSSFT_ERR_INVALID_ARG;
+  if (d->max_k < 1 || d->max_k > FPS_MAX_K || d->max_iters < 0) return FPSSFT_ERR_INVALID_ARG;
   if (!std::isfinite(d->zero_thresh) || d->zero_thresh < 0.f) return FPSSFT_ERR_INVALID_ARG;
   if (!std::isfinite(d->mag_rel_tol) || d->mag_rel_tol < 0.f) return FPSSFT_ERR_INVALID_ARG;
   if (!std::isfinite(d->grid_tol)) return FPSSFT_ERR_INVALID_ARG;
@@ -309,22 +309,22 @@ size_t solve_lds_bytes(const CubeDesc& c, int rec_cap, bool wave) {
   // The layout of carve_solve_lds: the D+1 spectra, and on the block path a
   // second buffer (the FFT's) or, with long lines, one line of scratch that
   // also holds the bin-list words; the twiddles; the constructed spectra of
-  // the time-domain construction-subtraction; the bin-list heads, largest
-  // amplitudes and entry counts (3 x L ints, each rounded to 8 bytes) and
-  // the fixed-point projection sums ((D+1) L int pairs, in the constructed
-  // spectra's buffer when there is one); per record slot the set entry; the
-  // exchange words and counters.
+  // the time-domain construction-subtraction; the bins' largest amplitudes
+  // and entry counts (2 x L ints, each rounded to 8 bytes) and the
+  // fixed-point projection sums ((D+1) L int pairs, in the constructed
+  // spectra's buffer when there is one); the record store (per slot the set
+  // entry, then the frequency hash); the exchange words and counters.
   const size_t lines = (size_t)(c.D + 1) * c.L;
   size_t b;
   if (c.serial) {
     b = (lines + c.L) * sizeof(float2);
   } else {
     b = (lines + (wave ? 0 : lines) + c.L + ((!wave && (c.flags & FPS_LITERAL_PEEL)) ? lines : 0)) * sizeof(float2);
-    b += 3 * (size_t)((c.L + 1) & ~1) * sizeof(int);
+    b += 2 * (size_t)((c.L + 1) & ~1) * sizeof(int);
     // the sums share the constructed spectra's buffer when there is one
     if (wave || !(c.flags & FPS_LITERAL_PEEL)) b += lines * 2 * sizeof(int);
   }
-  b += (size_t)rec_cap * FPS_REC_SLOT_BYTES(c.D);
+  b += (size_t)fps_rec_bytes(c.D, rec_cap);
   b += 64 * sizeof(int);
   return b;
 }
@@ -513,7 +513,7 @@ fpssft_status build_plan(const fpssft_desc* descs, int32_t batch, const fpssft_t
     } else {
       cd.rec_lds = 0;
       cd.rec_off = rec_ws_bytes;
-      rec_ws_bytes += ((int64_t)cd.max_k * FPS_REC_SLOT_BYTES(cd.D) + 255) / 256 * 256;
+      rec_ws_bytes += (fps_rec_bytes(cd.D, cd.max_k) + 255) / 256 * 256;
     }
     p->descs[c] = cd;
   }
@@ -821,7 +821,7 @@ fpssft_status fpssft_execute_noalloc(fpssft_plan_t p, int32_t cube, const void* 
   const int pre = (cd.serial || (cd.flags & FPS_LITERAL_PEEL)) ? 0 : std::min(cd.T, p->tune.chunk_iters);
   // the pre-chunk spectra, then the record store when it is not in LDS
   const size_t pre_span = ((size_t)pre * (cd.D + 1) * cd.L * sizeof(float2) + 255) / 256 * 256;
-  const size_t rec_bytes = cd.rec_lds ? 0 : (size_t)cd.max_k * FPS_REC_SLOT_BYTES(cd.D);
+  const size_t rec_bytes = cd.rec_lds ? 0 : (size_t)fps_rec_bytes(cd.D, cd.max_k);
   if (pre_span + rec_bytes > fpssft::kNoAllocScratchBytes) return FPSSFT_ERR_UNSUPPORTED;
   char* base = (char*)p->noalloc_scratch;
   float2* pre_buf = (float2*)base;

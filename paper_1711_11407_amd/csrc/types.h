@@ -59,6 +59,23 @@ struct OutPtrs {
 // frequency indices, canonical set index, bin-list link.
 #define FPS_REC_SLOT_BYTES(D) (8 + 4 * (D) + 2 * 4)
 
+// Largest record capacity (max_k) of a description.
+#define FPS_MAX_K (1 << 26)
+
+// Slots of the frequency hash of a record store of `cap` entries (open
+// addressing with linear probing, load factor at most 1/2): the smallest
+// power of two of at least 2 cap and 64; none without records.
+constexpr int32_t fps_rec_hash_slots(int32_t cap) {
+  int32_t h = 64;
+  while (h < 2 * cap) h <<= 1;
+  return cap > 0 ? h : 0;
+}
+
+// Bytes of a record store of `cap` entries: the slots, then the hash.
+constexpr int64_t fps_rec_bytes(int D, int32_t cap) {
+  return (int64_t)cap * FPS_REC_SLOT_BYTES(D) + 4 * (int64_t)fps_rec_hash_slots(cap);
+}
+
 // One work item of the line gather + FFT kernel: `count` iterations of one
 // cube starting at t0, written at element offset `out_off`.
 struct LineItem {

@@ -55,7 +55,7 @@ def test_noalloc_equals_execute_two_calls_shrinking(F):
 def test_noalloc_rejects_more_than_the_array(F):
     torch, dev = torch_dev()
     cube = W.plant((256, 256), 40, seed=94)
-    # records in device memory: 200000 slots of 24 bytes exceed 4 MiB
+    # records in device memory: 200000 slots of 24 bytes and their hash exceed 4 MiB
     spec = spec_for(F, cube.dims, 195, max_k=200000)
     plan = F.Plan([spec])
     x = torch.from_numpy(cube.x).to(dev)
