@@ -263,7 +263,8 @@ struct SolveLds {
   int2* Q;       // [(D+1) L] each bin's projection sums per line, fixed point
                  // (not with long lines)
   RecStore rec;  // the record store when it is in LDS
-  int* wsum;     // [2][16] per-wave exchange words, double-buffered
+  int* wsum;     // [2][16] per-wave exchange words (two per wave),
+                 // double-buffered
   int* cnt;      // [4]: slots appended; unused; set size after a pass that
                  // filled the store
 };
@@ -841,6 +842,49 @@ __device__ __forceinline__ void solve_cube(const CubeDesc& cd, const float2* __r
       int mslot[kNB], slot[kNB], bdet[kNB], bnew[kNB], wdet[kNB], wnew[kNB];
       int wall = 0;
       const unsigned long long lt = (1ull << lane) - 1ull;
+      // Bin j of the pass reads its spectra and subtracts its sums. With D
+      // <= 2 every bin does so before any is decoded, so that the LDS reads
+      // of all its bins overlap (more dimensions: the register budget). A bin
+      // without entries has zero sums, and subtracting exact zeros leaves r
+      // as it is.
+      constexpr bool kLoadAhead = D <= 2;
+      constexpr int kNR = kLoadAhead ? kNB : 1;
+      float2 rb[kNR][D + 1];
+      bool has[kNR];
+      auto load_bin = [&](int j, float2 (&r)[D + 1], bool& hs) {
+        const uint32_t m = m0 + (uint32_t)(j * B) + tid;
+        hs = false;
+        if (j < nbp && m < L) {
+#pragma unroll
+          for (int i = 0; i <= D; ++i) r[i] = S[i * L + m];
+          // entries of the set project onto this bin
+          if (serial) {
+            const int h = s.head[m];
+            hs = h >= 0;
+            if (hs) {
+              float2 sum[D + 1];
+              list_sum<D, kPow2, kRecLds>(g, ta, rs, tw, h, kc_set, bin_exponent(s.bmax[m]), sum);
+#pragma unroll
+              for (int i = 0; i <= D; ++i) r[i] = c_sub(r[i], sum[i]);
+            }
+          } else {
+            const int n = s.bcnt[m];
+            hs = n > 0;
+            if (!literal && (kLoadAhead || hs)) {
+              const int e = bin_exponent32(s.bmax[m], n);
+#pragma unroll
+              for (int i = 0; i <= D; ++i) {
+                const int2 q = s.Q[i * L + m];
+                r[i] = c_sub(r[i], make_float2(fixed_value32(q.x, e), fixed_value32(q.y, e)));
+              }
+            }
+          }
+        }
+      };
+      if constexpr (kLoadAhead) {
+#pragma unroll
+        for (int j = 0; j < kNB; ++j) load_bin(j, rb[j], has[j]);
+      }
 #pragma unroll
       for (int j = 0; j < kNB; ++j) {
         const uint32_t m = m0 + (uint32_t)(j * B) + tid;
@@ -851,28 +895,16 @@ __device__ __forceinline__ void solve_cube(const CubeDesc& cd, const float2* __r
         slot[j] = -1;
         if (j < nbp && m < L) {
           float2 r[D + 1];
+          bool hs;
+          if constexpr (kLoadAhead) {
 #pragma unroll
-          for (int i = 0; i <= D; ++i) r[i] = S[i * L + m];
-          // entries of the set project onto this bin
-          const int h = serial ? s.head[m] : -1;
-          const bool has = serial ? h >= 0 : s.bcnt[m] > 0;
-          if (has && !literal) {
-            float2 sum[D + 1];
-            if (serial) {
-              list_sum<D, kPow2, kRecLds>(g, ta, rs, tw, h, kc_set, bin_exponent(s.bmax[m]), sum);
-            } else {
-              const int e = bin_exponent32(s.bmax[m], s.bcnt[m]);
-#pragma unroll
-              for (int i = 0; i <= D; ++i) {
-                const int2 q = s.Q[i * L + m];
-                sum[i] = make_float2(fixed_value32(q.x, e), fixed_value32(q.y, e));
-              }
-            }
-#pragma unroll
-            for (int i = 0; i <= D; ++i) r[i] = c_sub(r[i], sum[i]);
+            for (int i = 0; i <= D; ++i) r[i] = rb[j][i];
+            hs = has[j];
+          } else {
+            load_bin(j, r, hs);
           }
           cand[j] = decode_bin<D, kPow2>(g, al, ta, r, m, th0, rho, gtol, tw, avg, nonzero, f[j], amp[j]);
-          if (has) {
+          if (hs) {
             // a frequency already in the set projects onto this bin
             if (cand[j]) mslot[j] = hash_find<D, kRecLds>(rs, freq_key<D>(g, f[j]), f[j]);
             if (serial) s.head[m] = -1;  // the list is rebuilt next iteration
@@ -922,32 +954,45 @@ __device__ __forceinline__ void solve_cube(const CubeDesc& cd, const float2* __r
           }
         }
       }
-      // exchange word: 7 bits each of the detection and new-frequency counts
-      // per bin set, the nonzero flag in bit 28
+      // exchange words of a wave: its detection counts per bin set in 16-bit
+      // fields (at most 64 each, at most 512 summed over 8 waves) with the
+      // nonzero flag in bit 31, and its new-frequency counts the same way
+      static_assert(kNB <= 2, "two 16-bit count fields per exchange word");
       const bool wnz = __ballot(nonzero ? 1 : 0) != 0ull;
-      int wword = wnz ? (1 << 28) : 0;
+      uint32_t wa = wnz ? 0x80000000u : 0u, wb = 0u;
 #pragma unroll
-      for (int j = 0; j < kNB; ++j) wword |= (wdet[j] | (wnew[j] << 7)) << (14 * j);
-      if (lane == 0) s.wsum[xpar * 16 + wv] = wword;
+      for (int j = 0; j < kNB; ++j) {
+        wa |= (uint32_t)wdet[j] << (16 * j);
+        wb |= (uint32_t)wnew[j] << (16 * j);
+      }
+      if (lane == 0) {
+        s.wsum[xpar * 16 + 2 * wv] = (int)wa;
+        s.wsum[xpar * 16 + 2 * wv + 1] = (int)wb;
+      }
       lds_barrier();
-      // one LDS read per lane, then the words are taken from the lanes
-      const int word = lane < nw ? s.wsum[xpar * 16 + lane] : 0;
+      // one LDS read per lane (zero past the last wave), then the words are
+      // taken from fixed lanes and summed as packed fields
+      const int word = lane < 2 * nw ? s.wsum[xpar * 16 + lane] : 0;
+      uint32_t sa = 0u, sb = 0u, pa = 0u, pb = 0u, fl = 0u;
+      const int wvu = __builtin_amdgcn_readfirstlane(wv);
+#pragma unroll
+      for (int w = 0; w < 8; ++w) {
+        const uint32_t va = (uint32_t)__builtin_amdgcn_readlane(word, 2 * w);
+        const uint32_t vb = (uint32_t)__builtin_amdgcn_readlane(word, 2 * w + 1);
+        fl |= va;
+        sa += va & 0x7fffffffu;
+        sb += vb;
+        pa += w < wvu ? (va & 0x7fffffffu) : 0u;
+        pb += w < wvu ? vb : 0u;
+      }
+      any = (fl >> 31) != 0u;
       int pdet[kNB], tdet[kNB], pnew[kNB], tnew[kNB];
 #pragma unroll
-      for (int j = 0; j < kNB; ++j) pdet[j] = tdet[j] = pnew[j] = tnew[j] = 0;
-      any = false;
-      for (int w = 0; w < nw; ++w) {
-        const int v = __builtin_amdgcn_readlane(word, w);
-#pragma unroll
-        for (int j = 0; j < kNB; ++j) {
-          const int cdn = (v >> (14 * j)) & 0x7f;
-          const int cnn = (v >> (14 * j + 7)) & 0x7f;
-          pdet[j] += (w < wv) ? cdn : 0;
-          pnew[j] += (w < wv) ? cnn : 0;
-          tdet[j] += cdn;
-          tnew[j] += cnn;
-        }
-        any |= ((v >> 28) & 1) != 0;
+      for (int j = 0; j < kNB; ++j) {
+        pdet[j] = (int)((pa >> (16 * j)) & 0xffffu);
+        tdet[j] = (int)((sa >> (16 * j)) & 0xffffu);
+        pnew[j] = (int)((pb >> (16 * j)) & 0xffffu);
+        tnew[j] = (int)((sb >> (16 * j)) & 0xffffu);
       }
       xpar ^= 1;
       int sum_det = 0, sum_new = 0;

@@ -150,6 +150,23 @@ def test_redetection_merged_like_the_oracle(F):
         assert np.abs(got_b["dropped_amps"]).max() <= specs[0].zero_thresh
 
 
+@pytest.mark.parametrize("max_k", [512, 20000])
+@pytest.mark.parametrize("threads", [256, 192, 128])
+def test_redetection_merged_every_path(F, threads, max_k):
+    """The merge of cube 148 on every solve path: spare waves linking beside
+    the transforms (256 threads), the wave path with links after the
+    transforms (192 = D+1 waves), the block path (128), each with the record
+    store and its frequency hash in LDS (max_k 512) or in device memory
+    (max_k 20000: 20000 x 24 bytes of slots exceed LDS)."""
+    cube = W.cfg4(only=[148])[0]
+    log(f"cube 148 threads={threads} max_k={max_k}")
+    plan, specs, xs = batched_setup(F, [cube], max_k=max_k, tuning=dict(block_threads=threads))
+    ref, _, _ = oracle_for(plan, 0, cube.x, specs[0])
+    assert ref.n == ref.k + 2 and len(ref.dropped_freqs) == 1
+    compare(plan.execute_batched(xs)[0].host(), ref, f"cube 148 batched threads={threads} max_k={max_k}")
+    compare(plan.execute(0, xs[0]).host(), ref, f"cube 148 plain threads={threads} max_k={max_k}")
+
+
 SHAPES = [dict(ndim=2, line_length=64, block_threads=192), dict(ndim=2, line_length=128, block_threads=320),
           dict(ndim=2, line_length=512, block_threads=512, lines_samples=1536)]
 
