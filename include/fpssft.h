@@ -241,8 +241,13 @@ fpssft_status fpssft_schedule_generate(const fpssft_desc* desc, int32_t T,
  * factorisations, and uploads them. `tuning` may be NULL.
  * Lines whose D+1 spectra, a second buffer and the twiddles do not fit in
  * LDS (160 KB) are transformed one line at a time, with the twiddles read
- * from device memory; UNSUPPORTED when even the D+1 spectra plus one line of
- * scratch do not fit ((D+2) L * 8 bytes > 160 KB, e.g. L > 6800 for D = 2).
+ * from device memory. When even the D+1 spectra plus one line of scratch do
+ * not fit ((D+2) L * 8 bytes > 160 KB, e.g. L > 6800 for D = 2), those
+ * buffers move to a device workspace of the plan ((D+2) L * 8 bytes per
+ * cube) and the radix passes of each line run through it; for such cubes
+ * fpssft_lines_fft and fpssft_lines_fft_all return UNSUPPORTED (their
+ * kernel transforms in LDS), and so does fpssft_amp_backward. Lines are
+ * at most 65536 points (L = LCM(N_k)), and N_k L < 2^31.
  * A cube's record store (max_k slots of 16 + 4 D bytes, one per set entry,
  * and a hash of the set's frequencies, 4 bytes a slot for the smallest
  * power of two of at least 2 max_k and 64 slots) stays in LDS when it fits
@@ -308,7 +313,8 @@ fpssft_status fpssft_execute(fpssft_plan_t plan, int32_t cube, const void* x,
  * streams, other threads) race and must be ordered by the caller. Nothing in
  * the array needs to start at zero. UNSUPPORTED when the cube needs more
  * than 4 MiB: chunk_iters (D+1) L * 8 bytes rounded up to 256, plus the
- * record store (above) when it exceeds LDS. Argument errors as for
+ * record store (above) when it exceeds LDS, plus the line workspace (above)
+ * of lines that exceed LDS. Argument errors as for
  * fpssft_execute. */
 fpssft_status fpssft_execute_noalloc(fpssft_plan_t plan, int32_t cube, const void* x,
                                      const fpssft_out* out, void* stream);

@@ -379,13 +379,15 @@ __device__ __forceinline__ void lds_barrier() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-// Forward, unnormalised FFT of `nl` contiguous lines of length L held in LDS
+// Forward, unnormalised FFT of `nl` contiguous lines of length L held in
 // buffer a (b is scratch of the same size); radix[] lists the stages (powers
 // of two only when kPow2). Returns the buffer holding the result. Whole
-// work-group; ends with a barrier.
+// work-group; ends with a barrier. The buffers are in LDS, or with `gmem`
+// in device memory, where each stage's barrier orders every memory access.
 template <bool kPow2>
 __device__ __forceinline__ float2* block_fft(float2* a, float2* b, int nl, int L, int nstages,
-                                             const int32_t* radix, const float2* __restrict__ tw) {
+                                             const int32_t* radix, const float2* __restrict__ tw,
+                                             bool gmem = false) {
   float2* in = a;
   float2* out = b;
   int Ns = 1;
@@ -399,7 +401,10 @@ __device__ __forceinline__ float2* block_fft(float2* a, float2* b, int nl, int L
       stage_fixed<2, kPow2>(in, out, nl, L, Ns, tw);
     else
       stage_generic(in, out, nl, L, Ns, r, tw);
-    lds_barrier();
+    if (gmem)
+      __syncthreads();
+    else
+      lds_barrier();
     float2* t = in;
     in = out;
     out = t;

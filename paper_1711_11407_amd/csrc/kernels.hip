@@ -248,6 +248,12 @@ __device__ __forceinline__ void rec_barrier() {
   else __syncthreads();
 }
 
+// Solve-kernel paths: the block FFT in LDS, one wave per line (registers),
+// and long lines whose spectra and scratch line are in a device workspace.
+constexpr int kPathBlock = 0;
+constexpr int kPathWave = 1;
+constexpr int kPathLinesWs = 2;
+
 struct SolveLds {
   float2* bufA;  // [(D+1) L] the line spectra, row i = line i
   float2* bufB;  // block path: the FFT's second buffer [(D+1) L]; long
@@ -275,13 +281,26 @@ struct SolveLds {
 // time-domain construction-subtraction, the per-bin words (largest
 // amplitudes, entry counts) and fixed-point projection sums, the records
 // with their frequency hash and the exchange words.
-template <int D, bool kWave>
-__device__ __forceinline__ SolveLds carve_solve_lds(char* smem, int L, int rec_cap, bool serial, bool literal) {
+template <int D, int kPath>
+__device__ __forceinline__ SolveLds carve_solve_lds(char* smem, int L, int rec_cap, bool serial, bool literal,
+                                                    char* lines_ws) {
+  constexpr bool kWave = kPath == kPathWave;
   SolveLds s;
   s.bufA = (float2*)smem;
   s.P = nullptr;
   float2* end;
-  if (!kWave && serial) {
+  if constexpr (kPath == kPathLinesWs) {
+    // lines longer still: the same buffers in device memory, LDS keeps the
+    // records only
+    s.bufA = (float2*)lines_ws;
+    s.bufB = s.bufA + (D + 1) * L;
+    s.tw = nullptr;
+    s.head = (int*)s.bufB;
+    s.bmax = (uint32_t*)(s.head + L);
+    s.bcnt = nullptr;
+    s.Q = nullptr;
+    end = (float2*)smem;
+  } else if (!kWave && serial) {
     s.bufB = s.bufA + (D + 1) * L;
     s.tw = nullptr;
     s.head = (int*)s.bufB;
@@ -637,11 +656,11 @@ __device__ __forceinline__ bool decode_bin(const Geo<D>& g, const uint32_t (&al)
 // opens a new entry. Every entry contributes to the one bin it projects
 // onto, so the subtraction is the same as summing every detection (the set
 // amplitudes are sums of detections).
-template <int D, bool kPow2, bool kRecLds, bool kWave>
+template <int D, bool kPow2, bool kRecLds, int kPath>
 __device__ __forceinline__ void solve_cube(const CubeDesc& cd, const float2* __restrict__ x, const OutPtrs out,
                                            const int32_t* __restrict__ sched, const float2* __restrict__ twall,
                                            const float2* __restrict__ pre, int pre_count, char* smem,
-                                           char* rec_store) {
+                                           char* rec_store, char* lines_ws) {
   const Geo<D> g = load_geo<D>(cd);
   const uint32_t L = g.L;
   const int T = cd.T;
@@ -655,12 +674,16 @@ __device__ __forceinline__ void solve_cube(const CubeDesc& cd, const float2* __r
   const int32_t* sch = sched + cd.sched_off;
   // Long lines (block path only): lines transformed one at a time, twiddles
   // read from global memory (the host sends no precomputed spectra).
-  const bool serial = !(kWave && kPow2) && cd.serial != 0;
+  constexpr bool kWave = kPath == kPathWave;
+  constexpr bool gmem = kPath == kPathLinesWs;  // the host sends only such cubes here
+  const bool serial = gmem || (!(kWave && kPow2) && cd.serial != 0);
   // Time-domain construction-subtraction (block path; the host sends such
   // cubes nowhere else) and line-averaged amplitudes.
   const bool literal = !(kWave && kPow2) && !serial && (cd.flags & FPS_LITERAL_PEEL) != 0;
   const bool avg = (cd.flags & FPS_AMP_AVERAGE) != 0;
-  SolveLds s = carve_solve_lds<D, kWave>(smem, (int)L, kRecLds ? cd.rec_lds : 0, serial, literal);
+  // Longer lines still: the spectra and the scratch line in device memory
+  // (barriers that order the line buffers then order every memory access).
+  SolveLds s = carve_solve_lds<D, kPath>(smem, (int)L, kRecLds ? cd.rec_lds : 0, serial, literal, lines_ws);
   const RecStore rs = kRecLds ? s.rec : carve_records<D>(rec_store, max_k);
   for (uint32_t e = tid; e <= rs.hmask; e += B) rs_st<kRecLds>(rs.ht, (int)e, -1);
   if (!serial) {
@@ -756,14 +779,22 @@ __device__ __forceinline__ void solve_cube(const CubeDesc& cd, const float2* __r
       rec_barrier<kRecLds>();
       S = s.bufA;
     } else if (serial) {
+      // the last iteration's reads of the line buffers come first
+      if (gmem) __syncthreads();
       for (int line = 0; line <= D; ++line) {
         gather_one_line<D, kPow2>(s.bufB, x, g, at, line, inv_L);
-        lds_barrier();
+        if (gmem)
+          __syncthreads();
+        else
+          lds_barrier();
         float2* dst = s.bufA + line * L;
-        const float2* R = block_fft<kPow2>(s.bufB, dst, 1, (int)L, cd.nstages, cd.radix, tw);
+        const float2* R = block_fft<kPow2>(s.bufB, dst, 1, (int)L, cd.nstages, cd.radix, tw, gmem);
         if (R != dst) {
           for (uint32_t e = tid; e < L; e += B) dst[e] = R[e];
-          lds_barrier();
+          if (gmem)
+            __syncthreads();
+          else
+            lds_barrier();
         }
       }
       S = s.bufA;
@@ -817,10 +848,16 @@ __device__ __forceinline__ void solve_cube(const CubeDesc& cd, const float2* __r
           s.head[e] = -1;
           s.bmax[e] = 0u;
         }
-        lds_barrier();
+        if (gmem)
+          __syncthreads();
+        else
+          lds_barrier();
       }
       link_bins<D, kPow2, kRecLds>(g, al, rs, s.head, s.bmax, serial ? nullptr : s.bcnt, tid, B, kc_set, hfrom);
-      rec_barrier<kRecLds>();
+      if (gmem)
+        __syncthreads();
+      else
+        rec_barrier<kRecLds>();
     }
     if (!serial && !literal && kc_set > 0) {
       // all threads add the entries' projections to their bins' sums
@@ -1155,13 +1192,14 @@ __device__ __forceinline__ void solve_cube(const CubeDesc& cd, const float2* __r
 // set for three waves per SIMD.
 #define FPS_SOLVE_ATTRS __attribute__((amdgpu_flat_work_group_size(64, 512), amdgpu_waves_per_eu(3, 3)))
 
-template <int D, bool kPow2, bool kRecLds, bool kWave>
+template <int D, bool kPow2, bool kRecLds, int kPath>
 __global__ FPS_SOLVE_ATTRS void k_solve_plain(const CubeDesc* __restrict__ descs, int cube, const float2* __restrict__ x,
                                               OutPtrs out, const int32_t* __restrict__ sched,
                                               const float2* __restrict__ tw, const float2* __restrict__ pre,
-                                              int pre_count, char* rec_store) {
+                                              int pre_count, char* rec_store, char* lines_ws) {
   extern __shared__ __attribute__((aligned(16))) char lds_solve[];
-  solve_cube<D, kPow2, kRecLds, kWave>(descs[cube], x, out, sched, tw, pre, pre_count, lds_solve, rec_store);
+  solve_cube<D, kPow2, kRecLds, kPath>(descs[cube], x, out, sched, tw, pre, pre_count, lds_solve, rec_store,
+                                       lines_ws);
 }
 
 // Persistent: work-group b first solves cube order[b] (the grid is at most
@@ -1171,7 +1209,7 @@ __global__ FPS_SOLVE_ATTRS void k_solve_plain(const CubeDesc* __restrict__ descs
 // Leaving, it counts itself in queue[1]; the last work-group out (every
 // other one has made its final take) sets both counters back to zero for
 // the next launch, so no reset kernel precedes the launch.
-template <int D, bool kPow2, bool kRecLds, bool kWave>
+template <int D, bool kPow2, bool kRecLds, int kPath>
 __global__ FPS_SOLVE_ATTRS void k_solve_batched(const CubeDesc* __restrict__ descs, const float2* const* __restrict__ xs,
                                                 const OutPtrs* __restrict__ outs, const int32_t* __restrict__ sched,
                                                 const float2* __restrict__ tw, const int32_t* __restrict__ order,
@@ -1195,8 +1233,10 @@ __global__ FPS_SOLVE_ATTRS void k_solve_batched(const CubeDesc* __restrict__ des
       break;
     }
     const int c = __builtin_amdgcn_readfirstlane(order[idx]);
-    solve_cube<D, kPow2, kRecLds, kWave>(descs[c], xs[c], outs[c], sched, tw, nullptr, 0, lds_solve,
-                                         kRecLds ? nullptr : recws + descs[c].rec_off);
+    const CubeDesc& cd = descs[c];
+    solve_cube<D, kPow2, kRecLds, kPath>(cd, xs[c], outs[c], sched, tw, nullptr, 0, lds_solve,
+                                         kRecLds ? nullptr : recws + cd.rec_off,
+                                         kPath == kPathLinesWs ? recws + cd.lws_off : nullptr);
   }
 }
 
@@ -1373,13 +1413,24 @@ __global__ void k_backward(const CubeDesc* __restrict__ descs, int cube, OutPtrs
 #define FPS_DISPATCH_SOLVE(key, ...)                                                          \
   FPS_DISPATCH_D(key.D, FPS_DISPATCH_B(key.rec_lds, kR, {                                     \
     if (key.pow2 && key.wave) {                                                               \
-      constexpr bool kP = true, kW = true;                                                    \
+      constexpr bool kP = true;                                                               \
+      constexpr int kW = kPathWave;                                                           \
+      __VA_ARGS__;                                                                            \
+    } else if (key.pow2 && key.lines_ws) {                                                    \
+      constexpr bool kP = true;                                                               \
+      constexpr int kW = kPathLinesWs;                                                        \
       __VA_ARGS__;                                                                            \
     } else if (key.pow2) {                                                                    \
-      constexpr bool kP = true, kW = false;                                                   \
+      constexpr bool kP = true;                                                               \
+      constexpr int kW = kPathBlock;                                                          \
+      __VA_ARGS__;                                                                            \
+    } else if (key.lines_ws) {                                                                \
+      constexpr bool kP = false;                                                              \
+      constexpr int kW = kPathLinesWs;                                                        \
       __VA_ARGS__;                                                                            \
     } else {                                                                                  \
-      constexpr bool kP = false, kW = false;                                                  \
+      constexpr bool kP = false;                                                              \
+      constexpr int kW = kPathBlock;                                                          \
       __VA_ARGS__;                                                                            \
     }                                                                                         \
   }))
@@ -1449,11 +1500,11 @@ hipError_t launch_lines_items(const LaunchCtx& ctx, const KernelKey& key, const 
 }
 
 hipError_t launch_solve_plain(const LaunchCtx& ctx, const KernelKey& key, int cube, const float2* x,
-                              const OutPtrs& out, const float2* pre, int pre_count, char* rec_store, size_t lds,
-                              int threads, hipStream_t st) {
+                              const OutPtrs& out, const float2* pre, int pre_count, char* rec_store, char* lines_ws,
+                              size_t lds, int threads, hipStream_t st) {
   FPS_DISPATCH_SOLVE(key, {
     hipLaunchKernelGGL((k_solve_plain<kD, kP, kR, kW>), dim3(1), dim3(threads), lds, st, ctx.descs, cube, x, out,
-                       ctx.sched, ctx.tw, pre, pre_count, rec_store);
+                       ctx.sched, ctx.tw, pre, pre_count, rec_store, lines_ws);
   })
   return hipGetLastError();
 }

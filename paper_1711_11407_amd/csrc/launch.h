@@ -12,7 +12,8 @@ struct LaunchCtx {
   const CubeDesc* descs;
   const int32_t* sched;
   const float2* tw;
-  char* rec_ws;  // record stores of the cubes whose records exceed LDS
+  char* rec_ws;  // record stores of the cubes whose records exceed LDS, and
+                 // line workspaces of the cubes whose lines do
 };
 
 // Which kernel instantiation serves a cube: dimension count, power-of-two
@@ -22,8 +23,9 @@ struct KernelKey {
   bool pow2;
   bool rec_lds;
   bool wave;  // solve kernels: one wave per line (64 <= L <= 512, >= D+1 waves)
+  bool lines_ws;  // solve kernels: lines in a device workspace (too long for LDS)
   bool operator==(const KernelKey& o) const {
-    return D == o.D && pow2 == o.pow2 && rec_lds == o.rec_lds && wave == o.wave;
+    return D == o.D && pow2 == o.pow2 && rec_lds == o.rec_lds && wave == o.wave && lines_ws == o.lines_ws;
   }
 };
 
@@ -46,8 +48,8 @@ hipError_t launch_lines_items(const LaunchCtx& ctx, const KernelKey& key, const 
                               const int32_t* ranges, int* queues, int grid, const float2* const* xs, float2* out,
                               int maxL, size_t lds, int threads, hipStream_t st);
 hipError_t launch_solve_plain(const LaunchCtx& ctx, const KernelKey& key, int cube, const float2* x,
-                              const OutPtrs& out, const float2* pre, int pre_count, char* rec_store, size_t lds,
-                              int threads, hipStream_t st);
+                              const OutPtrs& out, const float2* pre, int pre_count, char* rec_store, char* lines_ws,
+                              size_t lds, int threads, hipStream_t st);
 hipError_t launch_reset(int* p, int n, hipStream_t st);
 hipError_t launch_solve_batched(const LaunchCtx& ctx, const KernelKey& key, const float2* const* xs,
                                 const OutPtrs* outs, const int32_t* order, int ncubes, int* queue, int grid,

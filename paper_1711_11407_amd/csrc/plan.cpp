@@ -267,6 +267,7 @@ struct fpssft_plan_st {
   // the static scratch array of the allocation-free entry point on this
   // plan's device
   void* noalloc_scratch = nullptr;
+  bool has_lines_ws = false;  // some cube's lines live in device memory
   // batched path
   int32_t* d_order = nullptr;
   int* d_queue = nullptr;
@@ -316,7 +317,9 @@ size_t solve_lds_bytes(const CubeDesc& c, int rec_cap, bool wave) {
   // entry, then the frequency hash); the exchange words and counters.
   const size_t lines = (size_t)(c.D + 1) * c.L;
   size_t b;
-  if (c.serial) {
+  if (c.serial == 2) {
+    b = 0;  // spectra and scratch line in the device workspace
+  } else if (c.serial) {
     b = (lines + c.L) * sizeof(float2);
   } else {
     b = (lines + (wave ? 0 : lines) + c.L + ((!wave && (c.flags & FPS_LITERAL_PEEL)) ? lines : 0)) * sizeof(float2);
@@ -327,6 +330,12 @@ size_t solve_lds_bytes(const CubeDesc& c, int rec_cap, bool wave) {
   b += (size_t)fps_rec_bytes(c.D, rec_cap);
   b += 64 * sizeof(int);
   return b;
+}
+
+// Device workspace of a cube whose lines do not fit in LDS: its D+1 spectra
+// and one line of scratch, rounded to 256 bytes.
+size_t lines_ws_bytes(const CubeDesc& c) {
+  return ((size_t)(c.D + 2) * c.L * sizeof(float2) + 255) / 256 * 256;
 }
 
 size_t bwd_lds_bytes(const CubeDesc& c) {
@@ -343,7 +352,7 @@ size_t lines_single_lds_bytes(const CubeDesc& c) {
 fpssft::KernelKey key_of(const fpssft_plan_t p, int c) {
   const CubeDesc& cd = p->descs[c];
   const bool pow2 = cd.Lmask >= 0;
-  return fpssft::KernelKey{cd.D, pow2, cd.rec_lds > 0, uses_wave_path(p->cthreads[c], cd)};
+  return fpssft::KernelKey{cd.D, pow2, cd.rec_lds > 0, uses_wave_path(p->cthreads[c], cd), cd.serial == 2};
 }
 
 void destroy_plan(fpssft_plan_t p) {
@@ -497,14 +506,22 @@ fpssft_status build_plan(const fpssft_desc* descs, int32_t batch, const fpssft_t
     // twiddles in LDS are transformed one at a time (no precomputed chunk).
     cd.serial = 0;
     cd.rec_off = -1;
+    cd.lws_off = -1;
     if (!wave_eligible(cd) && solve_lds_bytes(cd, 0, false) > p->lds_max) cd.serial = 1;
+    // longer still: the spectra and the scratch line in device memory
+    if (cd.serial && solve_lds_bytes(cd, 0, false) > p->lds_max) {
+      cd.serial = 2;
+      cd.lws_off = rec_ws_bytes;
+      rec_ws_bytes += (int64_t)lines_ws_bytes(cd);
+      p->has_lines_ws = true;
+    }
     if (cd.serial && (cd.flags & FPS_LITERAL_PEEL)) return FPSSFT_ERR_UNSUPPORTED;
     // the time-domain construction-subtraction needs the samples themselves
     const int32_t pre_T = (cd.serial || (cd.flags & FPS_LITERAL_PEEL)) ? 0 : std::min(T, tn.chunk_iters);
     max_pre = std::max<int64_t>(max_pre, (int64_t)pre_T * (d.ndim + 1) * L);
     p->max_N = std::max(p->max_N, cd.N);
     const bool wave = uses_wave_path(p->cthreads[c], cd);
-    if (solve_lds_bytes(cd, 0, wave) > p->lds_max || lines_single_lds_bytes(cd) > p->lds_max)
+    if (solve_lds_bytes(cd, 0, wave) > p->lds_max || (cd.serial != 2 && lines_single_lds_bytes(cd) > p->lds_max))
       return FPSSFT_ERR_UNSUPPORTED;
     // The record store stays in LDS when the cube's spectra and records fit;
     // otherwise it is a region of the plan's device workspace.
@@ -567,6 +584,7 @@ fpssft_status build_plan(const fpssft_desc* descs, int32_t batch, const fpssft_t
     for (int i = g.first; i < g.first + g.count; ++i) {
       const int32_t c = order[i];
       const CubeDesc& cd = p->descs[c];
+      if (cd.serial == 2) continue;  // no line items: the line kernel needs LDS
       if (cd.serial)
         g.maxL_serial = std::max(g.maxL_serial, cd.L);
       else
@@ -808,7 +826,8 @@ fpssft_status fpssft_execute(fpssft_plan_t p, int32_t cube, const void* x, const
                                         lines_single_lds_bytes(cd), p->clthreads[cube], st));
   }
   char* rec = cd.rec_lds ? nullptr : p->d_recws + cd.rec_off;
-  HIP_TRY(fpssft::launch_solve_plain(p->ctx, key, cube, (const float2*)x, to_ptrs(*out), p->d_pre, pre, rec,
+  char* lws = cd.lws_off >= 0 ? p->d_recws + cd.lws_off : nullptr;
+  HIP_TRY(fpssft::launch_solve_plain(p->ctx, key, cube, (const float2*)x, to_ptrs(*out), p->d_pre, pre, rec, lws,
                                      g.lds_solve, g.threads, st));
   return FPSSFT_OK;
 }
@@ -819,13 +838,16 @@ fpssft_status fpssft_execute_noalloc(fpssft_plan_t p, int32_t cube, const void* 
   if (!on_plan_device(p)) return FPSSFT_ERR_INVALID_ARG;
   const CubeDesc& cd = p->descs[cube];
   const int pre = (cd.serial || (cd.flags & FPS_LITERAL_PEEL)) ? 0 : std::min(cd.T, p->tune.chunk_iters);
-  // the pre-chunk spectra, then the record store when it is not in LDS
+  // the pre-chunk spectra, the record store when it is not in LDS, then the
+  // line workspace when the lines are not
   const size_t pre_span = ((size_t)pre * (cd.D + 1) * cd.L * sizeof(float2) + 255) / 256 * 256;
-  const size_t rec_bytes = cd.rec_lds ? 0 : (size_t)fps_rec_bytes(cd.D, cd.max_k);
-  if (pre_span + rec_bytes > fpssft::kNoAllocScratchBytes) return FPSSFT_ERR_UNSUPPORTED;
+  const size_t rec_bytes = cd.rec_lds ? 0 : ((size_t)fps_rec_bytes(cd.D, cd.max_k) + 255) / 256 * 256;
+  const size_t lws_bytes = cd.lws_off >= 0 ? lines_ws_bytes(cd) : 0;
+  if (pre_span + rec_bytes + lws_bytes > fpssft::kNoAllocScratchBytes) return FPSSFT_ERR_UNSUPPORTED;
   char* base = (char*)p->noalloc_scratch;
   float2* pre_buf = (float2*)base;
   char* rec = cd.rec_lds ? nullptr : base + pre_span;
+  char* lws = cd.lws_off >= 0 ? base + pre_span + rec_bytes : nullptr;
   hipStream_t st = (hipStream_t)stream;
   const fpssft::KernelKey key = key_of(p, cube);
   const Group& g = p->groups[p->group_of[cube]];
@@ -833,7 +855,7 @@ fpssft_status fpssft_execute_noalloc(fpssft_plan_t p, int32_t cube, const void* 
     HIP_TRY(fpssft::launch_lines_single(p->ctx, key, cube, (const float2*)x, 0, pre, pre_buf, cd.L,
                                         lines_single_lds_bytes(cd), p->clthreads[cube], st));
   }
-  HIP_TRY(fpssft::launch_solve_plain(p->ctx, key, cube, (const float2*)x, to_ptrs(*out), pre_buf, pre, rec,
+  HIP_TRY(fpssft::launch_solve_plain(p->ctx, key, cube, (const float2*)x, to_ptrs(*out), pre_buf, pre, rec, lws,
                                      g.lds_solve, g.threads, st));
   return FPSSFT_OK;
 }
@@ -887,6 +909,7 @@ fpssft_status fpssft_lines_fft(fpssft_plan_t p, int32_t cube, const void* x, int
   if (!on_plan_device(p)) return FPSSFT_ERR_INVALID_ARG;
   const CubeDesc& cd = p->descs[cube];
   if (t0 < 0 || count < 0 || (int64_t)t0 + count > cd.T) return FPSSFT_ERR_INVALID_ARG;
+  if (cd.serial == 2) return FPSSFT_ERR_UNSUPPORTED;  // the line kernel transforms in LDS
   if (count == 0) return FPSSFT_OK;
   HIP_TRY(fpssft::launch_lines_single(p->ctx, key_of(p, cube), cube, (const float2*)x, t0, count,
                                       (float2*)spectra, cd.L, lines_single_lds_bytes(cd), p->clthreads[cube],
@@ -899,6 +922,7 @@ fpssft_status fpssft_lines_fft_all(fpssft_plan_t p, const void* const* xs, void*
   if (!on_plan_device(p)) return FPSSFT_ERR_INVALID_ARG;
   for (int c = 0; c < p->B; ++c)
     if (!xs[c]) return FPSSFT_ERR_INVALID_ARG;
+  if (p->has_lines_ws) return FPSSFT_ERR_UNSUPPORTED;  // the line kernel transforms in LDS
   hipStream_t st = (hipStream_t)stream;
   HIP_TRY(p->xs_tab.update(xs, st));
   HIP_TRY(fpssft::launch_reset(p->d_lqueue, 8 * (int)p->groups.size(), st));

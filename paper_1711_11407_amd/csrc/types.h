@@ -36,13 +36,18 @@ struct CubeDesc {
   int32_t sched_off;         // int32 offset of [T][2][D] in the schedule table
   int32_t tw_off;            // float2 offset of W_L in the twiddle table
   int32_t rec_lds;           // records kept in LDS (capacity), 0: global
-  int32_t serial;            // long lines: transformed one at a time through a
-                             // one-line scratch, twiddles read from global memory
+  int32_t serial;            // long lines, transformed one at a time through a
+                             // one-line scratch, twiddles read from global memory:
+                             // 1 with the spectra in LDS, 2 (longer) with the
+                             // spectra and the scratch in a device workspace
   uint32_t flags;            // FPSSFT_FLAG_* of the description
   int32_t pad1;
   int64_t spec_off;          // element offset in the packed spectra buffer
   int64_t rec_off;           // byte offset of the record store in the plan's
                              // device workspace (rec_lds == 0), else -1
+  int64_t lws_off;           // serial == 2: byte offset of the line workspace
+                             // ((D+2) L complex values) in the same workspace,
+                             // else -1
 };
 
 // Device pointers of one cube's outputs (same layout as fpssft_out).

@@ -244,6 +244,41 @@ def test_long_lines_plain_and_batched(F, dims, K, T):
     assert {tuple(f) for f in plain[0]["freqs"].tolist()} == {tuple(f) for f in cube.freqs.tolist()}
 
 
+# Lines too long for LDS even one at a time ((D+2) L * 8 bytes > 160 KB):
+# the D+1 spectra and the scratch line live in a device workspace of the
+# plan. Power-of-two and mixed-radix (3 * 2^14) lengths, 1-D to 3-D, records
+# in LDS and in device memory.
+LONGER = [((64, 16384), 100, 0, 512), ((32768,), 30, 3, 512), ((3, 16384), 40, 3, 512),
+          ((4, 4, 8192), 20, 0, 512), ((64, 16384), 100, 0, 20000)]
+
+
+@pytest.mark.parametrize("dims,K,T,max_k", LONGER)
+def test_lines_in_device_memory_plain_batched_noalloc(F, dims, K, T, max_k):
+    torch, dev = torch_dev()
+    cube = W.plant(dims, K, seed=500 + K, mag=(0.5, 1.5))
+    short = W.plant((64, 128), 30, seed=501)
+    specs = [spec_for(F, dims, 502, max_iters=T, max_k=max_k), spec_for(F, short.dims, 503, max_k=64)]
+    log(f"lines in device memory dims={dims} K={K} L={O.line_length(dims)} max_k={max_k}")
+    plan = F.Plan(specs)
+    xs = [torch.from_numpy(cube.x).to(dev), torch.from_numpy(short.x).to(dev)]
+    plain = [plan.execute(c, xs[c]).host() for c in range(2)]
+    batched = [o.host() for o in plan.execute_batched(xs)]
+    for c, x in enumerate((cube.x, short.x)):
+        ref, _, _ = oracle_for(plan, c, x, specs[c])
+        compare(plain[c], ref, f"plain {c}")
+        compare(batched[c], ref, f"batched {c}")
+    assert plain[0]["status"] == O.STATUS_OK
+    assert {tuple(f) for f in plain[0]["freqs"].tolist()} == {tuple(f) for f in cube.freqs.tolist()}
+    # the allocation-free entry point takes the workspace from its scratch
+    if max_k <= 512:
+        out = plan.alloc_result(0, dev)
+        got = plan.execute_noalloc(0, xs[0], out).host()
+        for k in ("k", "n", "iters", "status"):
+            assert got[k] == plain[0][k], k
+        np.testing.assert_array_equal(got["freqs"], plain[0]["freqs"])
+        np.testing.assert_array_equal(got["amps"], plain[0]["amps"])
+
+
 def test_long_lines_fft_matches_oracle_line_dft(F):
     torch, dev = torch_dev()
     dims = (512, 576)
