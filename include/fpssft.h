@@ -244,10 +244,12 @@ fpssft_status fpssft_schedule_generate(const fpssft_desc* desc, int32_t T,
  * from device memory. When even the D+1 spectra plus one line of scratch do
  * not fit ((D+2) L * 8 bytes > 160 KB, e.g. L > 6800 for D = 2), those
  * buffers move to a device workspace of the plan ((D+2) L * 8 bytes per
- * cube) and the radix passes of each line run through it; for such cubes
- * fpssft_lines_fft and fpssft_lines_fft_all return UNSUPPORTED (their
- * kernel transforms in LDS), and so does fpssft_amp_backward. Lines are
- * at most 65536 points (L = LCM(N_k)), and N_k L < 2^31.
+ * cube) and the radix passes of each line run through it.
+ * fpssft_lines_fft and fpssft_lines_fft_all keep two lines in LDS
+ * (2 L * 8 bytes) and return UNSUPPORTED for longer ones (L > 10240);
+ * fpssft_amp_backward returns UNSUPPORTED when 3 L * 8 + 8 max_k bytes
+ * exceed LDS. Lines are at most 65536 points (L = LCM(N_k)), and
+ * N_k L < 2^31.
  * A cube's record store (max_k slots of 16 + 4 D bytes, one per set entry,
  * and a hash of the set's frequencies, 4 bytes a slot for the smallest
  * power of two of at least 2 max_k and 64 slots) stays in LDS when it fits

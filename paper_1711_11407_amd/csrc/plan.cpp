@@ -267,7 +267,7 @@ struct fpssft_plan_st {
   // the static scratch array of the allocation-free entry point on this
   // plan's device
   void* noalloc_scratch = nullptr;
-  bool has_lines_ws = false;  // some cube's lines live in device memory
+  bool lines_too_long = false;  // some cube's lines exceed the line kernel's LDS
   // batched path
   int32_t* d_order = nullptr;
   int* d_queue = nullptr;
@@ -513,7 +513,6 @@ fpssft_status build_plan(const fpssft_desc* descs, int32_t batch, const fpssft_t
       cd.serial = 2;
       cd.lws_off = rec_ws_bytes;
       rec_ws_bytes += (int64_t)lines_ws_bytes(cd);
-      p->has_lines_ws = true;
     }
     if (cd.serial && (cd.flags & FPS_LITERAL_PEEL)) return FPSSFT_ERR_UNSUPPORTED;
     // the time-domain construction-subtraction needs the samples themselves
@@ -584,7 +583,11 @@ fpssft_status build_plan(const fpssft_desc* descs, int32_t batch, const fpssft_t
     for (int i = g.first; i < g.first + g.count; ++i) {
       const int32_t c = order[i];
       const CubeDesc& cd = p->descs[c];
-      if (cd.serial == 2) continue;  // no line items: the line kernel needs LDS
+      // the line kernel keeps two lines in LDS: longer ones get no items
+      if (lines_single_lds_bytes(cd) > p->lds_max) {
+        p->lines_too_long = true;
+        continue;
+      }
       if (cd.serial)
         g.maxL_serial = std::max(g.maxL_serial, cd.L);
       else
@@ -909,7 +912,7 @@ fpssft_status fpssft_lines_fft(fpssft_plan_t p, int32_t cube, const void* x, int
   if (!on_plan_device(p)) return FPSSFT_ERR_INVALID_ARG;
   const CubeDesc& cd = p->descs[cube];
   if (t0 < 0 || count < 0 || (int64_t)t0 + count > cd.T) return FPSSFT_ERR_INVALID_ARG;
-  if (cd.serial == 2) return FPSSFT_ERR_UNSUPPORTED;  // the line kernel transforms in LDS
+  if (lines_single_lds_bytes(cd) > p->lds_max) return FPSSFT_ERR_UNSUPPORTED;  // two lines in LDS
   if (count == 0) return FPSSFT_OK;
   HIP_TRY(fpssft::launch_lines_single(p->ctx, key_of(p, cube), cube, (const float2*)x, t0, count,
                                       (float2*)spectra, cd.L, lines_single_lds_bytes(cd), p->clthreads[cube],
@@ -922,7 +925,7 @@ fpssft_status fpssft_lines_fft_all(fpssft_plan_t p, const void* const* xs, void*
   if (!on_plan_device(p)) return FPSSFT_ERR_INVALID_ARG;
   for (int c = 0; c < p->B; ++c)
     if (!xs[c]) return FPSSFT_ERR_INVALID_ARG;
-  if (p->has_lines_ws) return FPSSFT_ERR_UNSUPPORTED;  // the line kernel transforms in LDS
+  if (p->lines_too_long) return FPSSFT_ERR_UNSUPPORTED;  // the line kernel keeps two lines in LDS
   hipStream_t st = (hipStream_t)stream;
   HIP_TRY(p->xs_tab.update(xs, st));
   HIP_TRY(fpssft::launch_reset(p->d_lqueue, 8 * (int)p->groups.size(), st));

@@ -98,10 +98,12 @@ def test_plan_limits(setup):
         F.Plan([spec_for(F, (65537, 2), 1)])
     assert e.value.status == UNSUPPORTED
     # lines too long for LDS even one at a time: planned with a device
-    # workspace; the line-FFT entry points (an LDS kernel) refuse them
-    big = F.Plan([spec_for(F, (8192, 8192), 1)])
+    # workspace (8192 x 8192, L = 8192; 3 x 16384, L = 49152); the line-FFT
+    # entry points keep two lines in LDS and refuse L = 49152
+    F.Plan([spec_for(F, (8192, 8192), 1)])
+    big = F.Plan([spec_for(F, (3, 16384), 1)])
     torch, dev = torch_dev()
-    xbig = torch.empty((8192, 8192), dtype=torch.complex64, device=dev)
+    xbig = torch.zeros((3, 16384), dtype=torch.complex64, device=dev)
     small_out = torch.empty(4, dtype=torch.complex64, device=dev)
     with pytest.raises(F.FpsSftError) as e:
         big.lines_fft(0, xbig, 0, 1, out=small_out)
@@ -109,7 +111,6 @@ def test_plan_limits(setup):
     with pytest.raises(F.FpsSftError) as e:
         big.lines_fft_all([xbig], out=small_out)
     assert e.value.status == UNSUPPORTED
-    del xbig
     # bad tuning values
     for tn in (dict(block_threads=96), dict(block_threads=1024), dict(max_radix=3), dict(lines_threads=32)):
         with pytest.raises(F.FpsSftError) as e:

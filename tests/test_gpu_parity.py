@@ -279,9 +279,12 @@ def test_lines_in_device_memory_plain_batched_noalloc(F, dims, K, T, max_k):
         np.testing.assert_array_equal(got["amps"], plain[0]["amps"])
 
 
-def test_long_lines_fft_matches_oracle_line_dft(F):
+@pytest.mark.parametrize("dims", [(512, 576), (64, 8192)])
+def test_long_lines_fft_matches_oracle_line_dft(F, dims):
+    """Line spectra of long lines against the FP64 line DFT: 512 x 576 (the
+    solve keeps its spectra in LDS) and 64 x 8192 (the solve keeps them in
+    device memory; the line kernel still holds its two lines in LDS)."""
     torch, dev = torch_dev()
-    dims = (512, 576)
     x = W.random_dense(dims, 17).astype(np.complex64)
     spec = spec_for(F, dims, 9, max_iters=4)
     plan = F.Plan([spec, spec_for(F, (64, 64), 10, max_iters=3)])
