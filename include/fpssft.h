@@ -247,9 +247,8 @@ fpssft_status fpssft_schedule_generate(const fpssft_desc* desc, int32_t T,
  * cube) and the radix passes of each line run through it.
  * fpssft_lines_fft and fpssft_lines_fft_all keep two lines in LDS
  * (2 L * 8 bytes) and return UNSUPPORTED for longer ones (L > 10240);
- * fpssft_amp_backward returns UNSUPPORTED when 3 L * 8 + 8 max_k bytes
- * exceed LDS. Lines are at most 65536 points (L = LCM(N_k)), and
- * N_k L < 2^31.
+ * fpssft_amp_backward puts its two line buffers in the same workspace.
+ * Lines are at most 65536 points (L = LCM(N_k)), and N_k L < 2^31.
  * A cube's record store (max_k slots of 16 + 4 D bytes, one per set entry,
  * and a hash of the set's frequencies, 4 bytes a slot for the smallest
  * power of two of at least 2 max_k and 64 slots) stays in LDS when it fits
@@ -356,9 +355,11 @@ fpssft_status fpssft_lines_fft_all(fpssft_plan_t plan, const void* const* xs,
  * it, all sums of detections; later entries ignored); grad_x: device
  * complex64 cube,
  * overwritten (zero off the sampled lines). UNSUPPORTED for
- * FPSSFT_FLAG_AMP_AVERAGE plans, and when a cube's line cotangent, FFT
- * scratch and twiddles plus its detection cotangents (24 L + 8 max_k
- * bytes) exceed 160 KB of LDS. */
+ * FPSSFT_FLAG_AMP_AVERAGE plans, and when a cube's LDS share exceeds
+ * 160 KB: its detection cotangents (8 max_k bytes) plus, unless its lines
+ * live in the plan's device workspace (above), the line cotangent and the
+ * FFT's second buffer (16 L bytes) and, for lines short enough to be
+ * transformed with all D+1 in LDS, the twiddles (8 L bytes). */
 fpssft_status fpssft_amp_backward(fpssft_plan_t plan, int32_t cube,
                                   const fpssft_out* fwd, const void* grad_amps,
                                   void* grad_x, void* stream);

@@ -1265,22 +1265,44 @@ __global__ void k_zero(float2* const* __restrict__ bufs, const int64_t* __restri
 // rotated by W^{p_j^{(t)}}, to the earlier detections j in that bin. The
 // line cotangent goes back through the 1/L DFT (an inverse DFT with 1/L) and
 // is added at the line-0 sample positions.
+//
+// The line cotangent and the FFT's second buffer are in LDS, with the
+// twiddles beside them, or for long lines read from device memory; with
+// kLinesWs (lines too long for LDS) the two line buffers are in the cube's
+// device workspace.
 // ---------------------------------------------------------------------------
-template <int D, bool kPow2>
+template <int D, bool kPow2, bool kLinesWs>
 __device__ __forceinline__ void backward_cube(const CubeDesc& cd, const OutPtrs fwd, const float2* __restrict__ ga,
                                               float2* __restrict__ gx, const int32_t* __restrict__ sched,
-                                              const float2* __restrict__ twall, char* smem) {
+                                              const float2* __restrict__ twall, char* smem, char* lines_ws) {
   const Geo<D> g = load_geo<D>(cd);
   const uint32_t L = g.L;
   const int tid = threadIdx.x;
   const int B = blockDim.x;
-  float2* rbar = (float2*)smem;  // [L] line-0 spectrum cotangent
-  float2* scratch = rbar + L;    // [L] FFT ping-pong
-  float2* tw = scratch + L;      // [L] twiddles
-  float2* abar = tw + L;         // [max_k] detection cotangents
+  const bool twg = kLinesWs || cd.serial != 0;   // twiddles from device memory
+  float2* rbar;     // [L] line-0 spectrum cotangent
+  float2* scratch;  // [L] FFT ping-pong
+  float2* abar;     // [max_k] detection cotangents (LDS)
+  const float2* tw;
+  if constexpr (kLinesWs) {
+    rbar = (float2*)lines_ws;
+    scratch = rbar + L;
+    abar = (float2*)smem;
+    tw = twall + cd.tw_off;
+  } else {
+    rbar = (float2*)smem;
+    scratch = rbar + L;
+    float2* twl = scratch + L;
+    abar = twg ? twl : twl + L;
+    if (twg) {
+      tw = twall + cd.tw_off;
+    } else {
+      for (uint32_t e = tid; e < L; e += B) twl[e] = ld_g(twall, cd.tw_off + e);
+      tw = twl;
+    }
+  }
   __shared__ int sh_s, sh_t;
 
-  for (uint32_t e = tid; e < L; e += B) tw[e] = ld_g(twall, cd.tw_off + e);
   // the set and the merged frequencies left out of it: every entry the
   // forward wrote is a sum of detections
   const int nent = min(max(ld_gi(fwd.info, 0), 0) + max(ld_gi(fwd.info, 4), 0), cd.max_k);
@@ -1343,7 +1365,7 @@ __device__ __forceinline__ void backward_cube(const CubeDesc& cd, const OutPtrs 
     //          = (1/L) conj(FFT(conj(r_bar)))(l).
     for (uint32_t m = tid; m < L; m += B) rbar[m] = c_scale(c_conj(rbar[m]), cd.inv_L);
     __syncthreads();
-    const float2* S = block_fft<kPow2>(rbar, scratch, 1, (int)L, cd.nstages, cd.radix, tw);
+    const float2* S = block_fft<kPow2>(rbar, scratch, 1, (int)L, cd.nstages, cd.radix, tw, kLinesWs);
     if (t_ok) {
       for (uint32_t l = tid; l < L; l += B) {
         int64_t step[D];
@@ -1358,19 +1380,20 @@ __device__ __forceinline__ void backward_cube(const CubeDesc& cd, const OutPtrs 
   }
 }
 
-template <int D, bool kPow2>
+template <int D, bool kPow2, bool kLinesWs>
 __global__ void k_backward(const CubeDesc* __restrict__ descs, int cube, OutPtrs fwd_single,
                            const float2* __restrict__ ga_single, float2* __restrict__ gx_single,
                            const int32_t* __restrict__ order, const OutPtrs* __restrict__ fwds,
                            const float2* const* __restrict__ gas, float2* const* __restrict__ gxs,
-                           const int32_t* __restrict__ sched, const float2* __restrict__ tw) {
+                           const int32_t* __restrict__ sched, const float2* __restrict__ tw, char* ws) {
   extern __shared__ __attribute__((aligned(16))) char lds_bwd[];
-  if (cube >= 0) {
-    backward_cube<D, kPow2>(descs[cube], fwd_single, ga_single, gx_single, sched, tw, lds_bwd);
-  } else {
-    const int c = order[blockIdx.x];
-    backward_cube<D, kPow2>(descs[c], fwds[c], gas[c], gxs[c], sched, tw, lds_bwd);
-  }
+  const int c = cube >= 0 ? cube : order[blockIdx.x];
+  const CubeDesc& cd = descs[c];
+  char* lws = kLinesWs ? ws + cd.lws_off : nullptr;
+  if (cube >= 0)
+    backward_cube<D, kPow2, kLinesWs>(cd, fwd_single, ga_single, gx_single, sched, tw, lds_bwd, lws);
+  else
+    backward_cube<D, kPow2, kLinesWs>(cd, fwds[c], gas[c], gxs[c], sched, tw, lds_bwd, lws);
 }
 
 // ---------------------------------------------------------------------------
@@ -1444,9 +1467,13 @@ const void* kernel_ptr(KernelKind kind, const KernelKey& key) {
     })
     return fn;
   }
-  FPS_DISPATCH_D(key.D, FPS_DISPATCH_B(key.pow2, kP, {
-    fn = kind == KernelKind::kLines ? (const void*)k_lines<kD, kP> : (const void*)k_backward<kD, kP>;
-  }))
+  if (kind == KernelKind::kBackward) {
+    FPS_DISPATCH_D(key.D, FPS_DISPATCH_B(key.pow2, kP, FPS_DISPATCH_B(key.lines_ws, kL, {
+      fn = (const void*)k_backward<kD, kP, kL>;
+    })))
+    return fn;
+  }
+  FPS_DISPATCH_D(key.D, FPS_DISPATCH_B(key.pow2, kP, { fn = (const void*)k_lines<kD, kP>; }))
   return fn;
 }
 
@@ -1544,11 +1571,11 @@ hipError_t launch_zero_multi(float2* const* bufs, const int64_t* lens, int nbufs
 
 hipError_t launch_backward_single(const LaunchCtx& ctx, const KernelKey& key, int cube, const OutPtrs& fwd,
                                   const float2* ga, float2* gx, size_t lds, int threads, hipStream_t st) {
-  FPS_DISPATCH_D(key.D, FPS_DISPATCH_B(key.pow2, kP, {
-    hipLaunchKernelGGL((k_backward<kD, kP>), dim3(1), dim3(threads), lds, st, ctx.descs, cube, fwd, ga, gx,
+  FPS_DISPATCH_D(key.D, FPS_DISPATCH_B(key.pow2, kP, FPS_DISPATCH_B(key.lines_ws, kL, {
+    hipLaunchKernelGGL((k_backward<kD, kP, kL>), dim3(1), dim3(threads), lds, st, ctx.descs, cube, fwd, ga, gx,
                        (const int32_t*)nullptr, (const OutPtrs*)nullptr, (const float2* const*)nullptr,
-                       (float2* const*)nullptr, ctx.sched, ctx.tw);
-  }))
+                       (float2* const*)nullptr, ctx.sched, ctx.tw, ctx.rec_ws);
+  })))
   return hipGetLastError();
 }
 
@@ -1556,10 +1583,11 @@ hipError_t launch_backward_batched(const LaunchCtx& ctx, const KernelKey& key, c
                                    const OutPtrs* fwds, const float2* const* gas, float2* const* gxs, size_t lds,
                                    int threads, hipStream_t st) {
   OutPtrs none{};
-  FPS_DISPATCH_D(key.D, FPS_DISPATCH_B(key.pow2, kP, {
-    hipLaunchKernelGGL((k_backward<kD, kP>), dim3(ncubes), dim3(threads), lds, st, ctx.descs, -1, none,
-                       (const float2*)nullptr, (float2*)nullptr, order, fwds, gas, gxs, ctx.sched, ctx.tw);
-  }))
+  FPS_DISPATCH_D(key.D, FPS_DISPATCH_B(key.pow2, kP, FPS_DISPATCH_B(key.lines_ws, kL, {
+    hipLaunchKernelGGL((k_backward<kD, kP, kL>), dim3(ncubes), dim3(threads), lds, st, ctx.descs, -1, none,
+                       (const float2*)nullptr, (float2*)nullptr, order, fwds, gas, gxs, ctx.sched, ctx.tw,
+                       ctx.rec_ws);
+  })))
   return hipGetLastError();
 }
 

@@ -338,8 +338,12 @@ size_t lines_ws_bytes(const CubeDesc& c) {
   return ((size_t)(c.D + 2) * c.L * sizeof(float2) + 255) / 256 * 256;
 }
 
+// LDS of the adjoint: the line cotangent and the FFT's second buffer (in the
+// line workspace when the lines are too long for LDS), the twiddles (read
+// from device memory for long lines), the detection cotangents.
 size_t bwd_lds_bytes(const CubeDesc& c) {
-  return 3 * (size_t)c.L * sizeof(float2) + (size_t)c.max_k * sizeof(float2) + 64;
+  const size_t lines = c.serial == 2 ? 0 : (c.serial ? 2 : 3) * (size_t)c.L * sizeof(float2);
+  return lines + (size_t)c.max_k * sizeof(float2) + 64;
 }
 
 // Line-FFT work-group LDS: two line buffers and the twiddle table.

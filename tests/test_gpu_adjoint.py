@@ -155,3 +155,42 @@ def test_amp_backward_with_redetection(F):
     err = np.linalg.norm(g - gref) / np.linalg.norm(gref)
     log(f"re-detection cube: {len(pos)} touched samples, grad rel L2 err={err:.2e}")
     assert err <= GRAD_TOL
+
+
+@pytest.mark.parametrize("dims,K", [((512, 576), 40), ((64, 8192), 30), ((64, 16384), 30)])
+def test_amp_backward_long_lines(F, dims, K):
+    """The adjoint on long lines: 512 x 576 (L = 4608: lines in LDS,
+    twiddles from device memory) and 64 x 8192, 64 x 16384 (lines in the
+    cube's device workspace). Checked by the dot-product identity
+    <y, M x> = <M^H y, x>, against the FP64 finite-difference gradient of
+    sum |a|^2 at 24 sampled touched positions, and zero off them."""
+    torch, dev = torch_dev()
+    cube = W.plant(dims, K, seed=700 + K)
+    spec = spec_for(F, dims, 701, max_k=128)
+    plan = F.Plan([spec])
+    log(f"adjoint long lines {dims} L={O.line_length(dims)}")
+    x = torch.from_numpy(cube.x).to(dev)
+    res = plan.execute(0, x)
+    h = res.host()
+    ref, al, ta = oracle_for(plan, 0, cube.x, spec)
+    compare(h, ref, f"forward {dims}")
+    rng = np.random.default_rng(2)
+    y = (rng.standard_normal(spec.max_k) + 1j * rng.standard_normal(spec.max_k)).astype(np.complex64)
+    y[h["k"]:] = 0
+    xt = plan.amp_backward(0, res, torch.from_numpy(y).to(dev)).cpu().numpy().astype(np.complex128)
+    lhs = np.vdot(y[:h["k"]].astype(np.complex128), h["amps"].astype(np.complex128))
+    rhs = np.vdot(xt.reshape(-1), cube.x.reshape(-1).astype(np.complex128))
+    assert abs(lhs - rhs) / abs(lhs) < 1e-5
+    # gradient of sum |a|^2 through autograd, against finite differences
+    xg = torch.from_numpy(cube.x).to(dev).requires_grad_(True)
+    amps, _, _ = F.sft_amplitudes(plan, 0, xg)
+    (amps.abs() ** 2).sum().backward()
+    g = xg.grad.cpu().numpy().astype(np.complex128).reshape(-1)
+    pos = O.touched_positions(cube.x.shape, ref.rec_iter, al, ta)
+    sample = rng.choice(pos, size=min(24, len(pos)), replace=False)
+    gref = O.grad_sum_abs2_fd(cube.x.astype(np.complex128), ref, al, ta, positions=sample).reshape(-1)
+    err = np.linalg.norm(g[sample] - gref[sample]) / np.linalg.norm(gref[sample])
+    assert err <= GRAD_TOL, err
+    mask = np.ones(g.size, bool)
+    mask[pos] = False
+    assert np.all(g[mask] == 0)
