@@ -879,49 +879,6 @@ __device__ __forceinline__ void solve_cube(const CubeDesc& cd, const float2* __r
       int mslot[kNB], slot[kNB], bdet[kNB], bnew[kNB], wdet[kNB], wnew[kNB];
       int wall = 0;
       const unsigned long long lt = (1ull << lane) - 1ull;
-      // Bin j of the pass reads its spectra and subtracts its sums. With D
-      // <= 2 every bin does so before any is decoded, so that the LDS reads
-      // of all its bins overlap (more dimensions: the register budget). A bin
-      // without entries has zero sums, and subtracting exact zeros leaves r
-      // as it is.
-      constexpr bool kLoadAhead = D <= 2;
-      constexpr int kNR = kLoadAhead ? kNB : 1;
-      float2 rb[kNR][D + 1];
-      bool has[kNR];
-      auto load_bin = [&](int j, float2 (&r)[D + 1], bool& hs) {
-        const uint32_t m = m0 + (uint32_t)(j * B) + tid;
-        hs = false;
-        if (j < nbp && m < L) {
-#pragma unroll
-          for (int i = 0; i <= D; ++i) r[i] = S[i * L + m];
-          // entries of the set project onto this bin
-          if (serial) {
-            const int h = s.head[m];
-            hs = h >= 0;
-            if (hs) {
-              float2 sum[D + 1];
-              list_sum<D, kPow2, kRecLds>(g, ta, rs, tw, h, kc_set, bin_exponent(s.bmax[m]), sum);
-#pragma unroll
-              for (int i = 0; i <= D; ++i) r[i] = c_sub(r[i], sum[i]);
-            }
-          } else {
-            const int n = s.bcnt[m];
-            hs = n > 0;
-            if (!literal && (kLoadAhead || hs)) {
-              const int e = bin_exponent32(s.bmax[m], n);
-#pragma unroll
-              for (int i = 0; i <= D; ++i) {
-                const int2 q = s.Q[i * L + m];
-                r[i] = c_sub(r[i], make_float2(fixed_value32(q.x, e), fixed_value32(q.y, e)));
-              }
-            }
-          }
-        }
-      };
-      if constexpr (kLoadAhead) {
-#pragma unroll
-        for (int j = 0; j < kNB; ++j) load_bin(j, rb[j], has[j]);
-      }
 #pragma unroll
       for (int j = 0; j < kNB; ++j) {
         const uint32_t m = m0 + (uint32_t)(j * B) + tid;
@@ -932,13 +889,25 @@ __device__ __forceinline__ void solve_cube(const CubeDesc& cd, const float2* __r
         slot[j] = -1;
         if (j < nbp && m < L) {
           float2 r[D + 1];
-          bool hs;
-          if constexpr (kLoadAhead) {
 #pragma unroll
-            for (int i = 0; i <= D; ++i) r[i] = rb[j][i];
-            hs = has[j];
-          } else {
-            load_bin(j, r, hs);
+          for (int i = 0; i <= D; ++i) r[i] = S[i * L + m];
+          // entries of the set project onto this bin
+          const int h = serial ? s.head[m] : -1;
+          const bool hs = serial ? h >= 0 : s.bcnt[m] > 0;
+          if (hs && !literal) {
+            float2 sum[D + 1];
+            if (serial) {
+              list_sum<D, kPow2, kRecLds>(g, ta, rs, tw, h, kc_set, bin_exponent(s.bmax[m]), sum);
+            } else {
+              const int e = bin_exponent32(s.bmax[m], s.bcnt[m]);
+#pragma unroll
+              for (int i = 0; i <= D; ++i) {
+                const int2 q = s.Q[i * L + m];
+                sum[i] = make_float2(fixed_value32(q.x, e), fixed_value32(q.y, e));
+              }
+            }
+#pragma unroll
+            for (int i = 0; i <= D; ++i) r[i] = c_sub(r[i], sum[i]);
           }
           cand[j] = decode_bin<D, kPow2>(g, al, ta, r, m, th0, rho, gtol, tw, avg, nonzero, f[j], amp[j]);
           if (hs) {
