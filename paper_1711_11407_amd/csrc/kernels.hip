@@ -1213,14 +1213,23 @@ __global__ void k_reset(int* __restrict__ p, int n) {
   for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
 }
 
-// Zero fill of one buffer per blockIdx.y (float2 elements).
+// Zero fill of one buffer per blockIdx.y (float2 elements): 16-byte stores
+// of two elements, after one leading element when the buffer is only 8-byte
+// aligned, and a trailing one when the rest is odd.
 __global__ void k_zero(float2* const* __restrict__ bufs, const int64_t* __restrict__ lens, float2* single,
                        int64_t single_len) {
   float2* p = single ? single : bufs[blockIdx.y];
   const int64_t n = single ? single_len : lens[blockIdx.y];
+  if (n <= 0) return;
+  const int64_t head = ((uintptr_t)p & 15u) ? 1 : 0;
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (head && gid == 0) st_g(p, 0, make_float2(0.f, 0.f));
+  float2* q = p + head;
+  const int64_t m = n - head;
+  const int64_t pairs = m >> 1;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
-    st_g(p, i, make_float2(0.f, 0.f));
+  for (int64_t i = gid; i < pairs; i += stride) st_g_pair(q, 2 * i, make_float2(0.f, 0.f), make_float2(0.f, 0.f));
+  if ((m & 1) && gid == 0) st_g(q, m - 1, make_float2(0.f, 0.f));
 }
 
 // ---------------------------------------------------------------------------
@@ -1521,7 +1530,8 @@ hipError_t launch_solve_batched(const LaunchCtx& ctx, const KernelKey& key, cons
 }
 
 hipError_t launch_zero_single(float2* p, int64_t n, hipStream_t st) {
-  int64_t blocks = (n + 255) / 256;
+  // about four 16-byte stores per thread
+  int64_t blocks = (n + 2047) / 2048;
   if (blocks > 4096) blocks = 4096;
   if (blocks < 1) blocks = 1;
   hipLaunchKernelGGL(k_zero, dim3((unsigned)blocks), dim3(256), 0, st, (float2* const*)nullptr,
@@ -1530,7 +1540,8 @@ hipError_t launch_zero_single(float2* p, int64_t n, hipStream_t st) {
 }
 
 hipError_t launch_zero_multi(float2* const* bufs, const int64_t* lens, int nbufs, int64_t maxlen, hipStream_t st) {
-  int64_t blocks = (maxlen + 255) / 256;
+  // about four 16-byte stores per thread
+  int64_t blocks = (maxlen + 2047) / 2048;
   if (blocks > 512) blocks = 512;
   if (blocks < 1) blocks = 1;
   hipLaunchKernelGGL(k_zero, dim3((unsigned)blocks, nbufs), dim3(256), 0, st, bufs, lens, (float2*)nullptr,
