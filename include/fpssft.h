@@ -321,8 +321,9 @@ fpssft_status fpssft_execute_noalloc(fpssft_plan_t plan, int32_t cube, const voi
                                      const fpssft_out* out, void* stream);
 
 /* The same method (Sec. 2.2) for all cubes of the plan in one persistent
- * launch per kernel instantiation (work-groups take cubes from a device
- * queue, shortest lines first), replayed from a HIP graph or launched
+ * launch per kernel instantiation (each work-group solves the cube of its
+ * index in an order of shortest lines first, then takes the next ones from
+ * a device queue), replayed from a HIP graph or launched
  * directly (fpssft_tuning). xs: host array of `batch` device cube pointers;
  * outs: host array of `batch` output structs (device pointers inside).
  * Results equal fpssft_execute's cube by cube, bit for bit. */

@@ -7,21 +7,23 @@
 //                   spectra (precomputed by k_lines for the first chunk,
 //                   gathered and transformed after it: one wave per line in
 //                   registers, a block FFT in LDS, or line by line for long
-//                   lines), the subtraction of the recovered set
-//                   (construction-subtraction, Sec. 2.2: on the spectra,
-//                   through per-bin lists summed exactly, or in time on
+//                   lines, in LDS or in a device workspace), the subtraction
+//                   of the recovered set (construction-subtraction, Sec. 2.2:
+//                   on the spectra as exact per-bin sums, or in time on
 //                   request), the 1-sparsity test, the phase decode and the
 //                   amplitude (Eq. decoding), the merge of a frequency
-//                   detected again, the ordered record, and the stopping
-//                   rule.
-//  k_solve_batched  the same per cube, persistent: work-groups take cube
-//                   indices from a device queue until it is empty.
+//                   detected again (found through a hash of the set's
+//                   frequencies), the ordered record, and the stopping rule.
+//  k_solve_batched  the same per cube, persistent: each work-group solves
+//                   the cube of its index, then takes cube indices from a
+//                   device queue until it is empty.
 //  k_backward       adjoint of the set amplitudes with the decisions fixed.
 //  k_reset, k_zero  counter reset and zero fill (kernels, so that they can
 //                   sit inside a captured graph).
 //
-// Kernels are instantiated per (D, power-of-two L, records in LDS, wave
-// path); the host groups cubes by instantiation.
+// Kernels are instantiated per (D, power-of-two L, records in LDS, path:
+// block FFT, wave per line, or lines in a device workspace); the host groups
+// cubes by instantiation.
 #include <hip/hip_runtime.h>
 
 #include <mutex>
@@ -336,11 +338,12 @@ __device__ __forceinline__ SolveLds carve_solve_lds(char* smem, int L, int rec_c
   return s;
 }
 
-// Exact, order-independent sums of the records' projections on one bin:
-// each term is truncated to an integer multiple of 2^-e in 32 bits, the
-// integers are added in 64 bits, and the sum is converted back once, so the
-// result does not depend on the order of a list. The scale comes from the
-// largest amplitude component in the bin's list (amax < 2^ea): a term is
+// Exact, order-independent sums of the records' projections on one bin
+// (long lines, where a bin's owner sums its list): each term is truncated to
+// an integer multiple of 2^-e in 32 bits, the integers are added in 64 bits,
+// and the sum is converted back once, so the result does not depend on the
+// order of the list. The scale comes from the largest amplitude component
+// in the bin's list (amax < 2^ea): a term is
 // below sqrt(2) amax < 2^(ea + 1), so e = 29 - ea keeps it below 2^30, and
 // the truncation error of a term is below 2^(ea - 29), about 4e-9 of amax.
 __device__ __forceinline__ int bin_exponent(uint32_t amax_bits) {
@@ -768,7 +771,7 @@ __device__ __forceinline__ void solve_cube(const CubeDesc& cd, const float2* __r
         }
         // The next iteration's gathers are issued after the transform: in
         // flight, scattered loads slow this wave's LDS traffic several-fold;
-        // they overlap the list links and the decode instead.
+        // they overlap the entry counts, the sums and the decode instead.
         if (t + 1 < T)
           wave_prefetch<D, kPow2>(pfw, E, g, x, at + 2 * D, pre + (int64_t)(t + 1) * (D + 1) * L, t + 1 < pre_count,
                                   wv);
