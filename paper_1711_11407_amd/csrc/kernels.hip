@@ -1264,6 +1264,9 @@ __device__ __forceinline__ void backward_cube(const CubeDesc& cd, const OutPtrs 
   float2* rbar;     // [L] line-0 spectrum cotangent
   float2* scratch;  // [L] FFT ping-pong
   float2* abar;     // [max_k] detection cotangents (LDS)
+  int* riter;       // [max_k] detection iterations (LDS, after abar)
+  uint32_t* dgk;    // [max_k][D] c_k m_k of each detection's frequency
+                    // (LDS); ~0 first: no valid set index
   const float2* tw;
   if constexpr (kLinesWs) {
     rbar = (float2*)lines_ws;
@@ -1282,6 +1285,8 @@ __device__ __forceinline__ void backward_cube(const CubeDesc& cd, const OutPtrs 
       tw = twl;
     }
   }
+  riter = (int*)(abar + cd.max_k);
+  dgk = (uint32_t*)(riter + cd.max_k);
   __shared__ int sh_s, sh_t;
 
   // the set and the merged frequencies left out of it: every entry the
@@ -1293,15 +1298,26 @@ __device__ __forceinline__ void backward_cube(const CubeDesc& cd, const OutPtrs 
   for (int i = tid; i < n; i += B) {
     const int si = ld_gi(fwd.rec_sin, i);
     abar[i] = (si >= 0 && si < nent) ? ld_g(ga, si) : make_float2(0.f, 0.f);
+    riter[i] = ld_gi(fwd.rec_iter, i);
+    const bool fok = si >= 0 && si < cd.max_k;
+#pragma unroll
+    for (int q = 0; q < D; ++q)
+      dgk[i * D + q] = fok ? g.c[q] * (uint32_t)ld_gi(fwd.freqs, si * D + q) : (q == 0 ? ~0u : 0u);
   }
   __syncthreads();
   int e = n;
   while (e > 0) {
     if (tid == 0) {
-      const int tt = ld_gi(fwd.rec_iter, e - 1);
-      int s0 = e - 1;
-      while (s0 > 0 && ld_gi(fwd.rec_iter, s0 - 1) == tt) --s0;
-      sh_s = s0;
+      // the detections of iteration tt are the run ending at e - 1 (the
+      // trace is in iteration order): binary search for its first index
+      const int tt = riter[e - 1];
+      int lo = 0, hi = e - 1;  // riter[hi] == tt
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (riter[mid] < tt) lo = mid + 1;
+        else hi = mid;
+      }
+      sh_s = lo;
       sh_t = tt;
     }
     for (uint32_t m = tid; m < L; m += B) rbar[m] = make_float2(0.f, 0.f);
@@ -1319,22 +1335,20 @@ __device__ __forceinline__ void backward_cube(const CubeDesc& cd, const OutPtrs 
     // Detections of iteration t: distinct bins, so plain stores.
     for (int i = s0 + tid; i < e; i += B) {
       const int m = ld_gi(fwd.rec_bin, i);
-      const int si = ld_gi(fwd.rec_sin, i);
-      if (!t_ok || m < 0 || m >= (int)L || si < 0 || si >= cd.max_k) continue;
+      if (!t_ok || m < 0 || m >= (int)L || dgk[i * D] == ~0u) continue;
       uint32_t p = 0;
 #pragma unroll
-      for (int q = 0; q < D; ++q) p = umod<kPow2>(p + ta[q] * (g.c[q] * (uint32_t)ld_gi(fwd.freqs, si * D + q)), L);
+      for (int q = 0; q < D; ++q) p = umod<kPow2>(p + ta[q] * dgk[i * D + q], L);
       rbar[m] = c_mulc(abar[i], tw[p]);
     }
     __syncthreads();
     // Earlier detections that iteration t's construction-subtraction removed.
     for (int j = tid; j < s0; j += B) {
-      const int si = ld_gi(fwd.rec_sin, j);
-      if (si < 0 || si >= cd.max_k) continue;
+      if (dgk[j * D] == ~0u) continue;
       uint32_t b = 0, p = 0;
 #pragma unroll
       for (int q = 0; q < D; ++q) {
-        const uint32_t gq = g.c[q] * (uint32_t)ld_gi(fwd.freqs, si * D + q);
+        const uint32_t gq = dgk[j * D + q];
         b = umod<kPow2>(b + al[q] * gq, L);
         p = umod<kPow2>(p + ta[q] * gq, L);
       }
