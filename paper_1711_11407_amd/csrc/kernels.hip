@@ -583,7 +583,9 @@ __device__ __forceinline__ void list_sum(const Geo<D>& g, const uint32_t (&ta)[D
 // nonzero and magnitude-equality tests (Sec. 2.1), the phase decode of the
 // frequency (Eq. decoding) with the on-grid check, the projection-consistency
 // check, and the amplitude r_0 exp(-j 2 pi q / L) (with `avg`, the mean over
-// the D+1 lines of r_i exp(-j 2 pi q_i / L)). All decisions in float32.
+// the D+1 lines of r_i exp(-j 2 pi q_i / L)). All decisions in float32; the
+// magnitudes take the hardware square root (within 1 ulp), without the
+// correctly rounded expansion.
 template <int D, bool kPow2>
 __device__ __forceinline__ bool decode_bin(const Geo<D>& g, const uint32_t (&al)[D], const uint32_t (&ta)[D],
                                            const float2 (&r)[D + 1], uint32_t m, float th0, float rho, float gtol,
@@ -591,13 +593,13 @@ __device__ __forceinline__ bool decode_bin(const Geo<D>& g, const uint32_t (&al)
                                            float2& amp) {
   const uint32_t L = g.L;
   const float2 r0 = r[0];
-  const float mag0 = sqrtf(r0.x * r0.x + r0.y * r0.y);
+  const float mag0 = __builtin_amdgcn_sqrtf(r0.x * r0.x + r0.y * r0.y);
   nonzero |= mag0 > th0;
   bool cand = mag0 > th0;
 #pragma unroll
   for (int k = 0; k < D; ++k) {
     const float2 ri = r[k + 1];
-    const float mi = sqrtf(ri.x * ri.x + ri.y * ri.y);
+    const float mi = __builtin_amdgcn_sqrtf(ri.x * ri.x + ri.y * ri.y);
     nonzero |= mi > th0;
     cand = cand && (fabsf(mi - mag0) <= rho * mag0);
   }
@@ -896,18 +898,35 @@ __device__ __forceinline__ void solve_cube(const CubeDesc& cd, const float2* __r
           for (int i = 0; i <= D; ++i) r[i] = S[i * L + m];
           // entries of the set project onto this bin
           const int h = serial ? s.head[m] : -1;
-          const bool hs = serial ? h >= 0 : s.bcnt[m] > 0;
+          // The bin's count, scale word and sums are read together (only the
+          // count decides whether they are used), except where the block
+          // path's registers are short (D >= 3).
+          constexpr bool kEarly = (kWave && kPow2) || D <= 2;
+          int nb = 0;
+          uint32_t bm = 0u;
+          int2 q[D + 1];
+          if (!serial) {
+            nb = s.bcnt[m];
+            if constexpr (kEarly) {
+              bm = s.bmax[m];
+#pragma unroll
+              for (int i = 0; i <= D; ++i) q[i] = s.Q[i * L + m];
+            }
+          }
+          const bool hs = serial ? h >= 0 : nb > 0;
           if (hs && !literal) {
             float2 sum[D + 1];
             if (serial) {
               list_sum<D, kPow2, kRecLds>(g, ta, rs, tw, h, kc_set, bin_exponent(s.bmax[m]), sum);
             } else {
-              const int e = bin_exponent32(s.bmax[m], s.bcnt[m]);
+              if constexpr (!kEarly) {
+                bm = s.bmax[m];
 #pragma unroll
-              for (int i = 0; i <= D; ++i) {
-                const int2 q = s.Q[i * L + m];
-                sum[i] = make_float2(fixed_value32(q.x, e), fixed_value32(q.y, e));
+                for (int i = 0; i <= D; ++i) q[i] = s.Q[i * L + m];
               }
+              const int e = bin_exponent32(bm, nb);
+#pragma unroll
+              for (int i = 0; i <= D; ++i) sum[i] = make_float2(fixed_value32(q[i].x, e), fixed_value32(q[i].y, e));
             }
 #pragma unroll
             for (int i = 0; i <= D; ++i) r[i] = c_sub(r[i], sum[i]);
