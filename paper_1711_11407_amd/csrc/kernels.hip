@@ -506,6 +506,47 @@ __device__ __forceinline__ void link_bins(const Geo<D>& g, const uint32_t (&al)[
   }
 }
 
+// One entry's contribution: the bin, the fixed-point scale and the terms on
+// the D+1 lines. Every read comes before the first atomic (the compiler does
+// not move reads across them), so that they go out in one round.
+template <int D, bool kPow2, bool kRecLds>
+__device__ __forceinline__ uint32_t entry_reads(const Geo<D>& g, const uint32_t (&al)[D], const uint32_t (&ta)[D],
+                                                const RecStore& rs, const float2* tw, const uint32_t* bmax,
+                                                const int* bcnt, int j, float2& a, uint32_t& bm, int& bc,
+                                                float2 (&w)[D + 1]) {
+  const uint32_t L = g.L;
+  uint32_t gk[D];
+  uint32_t b = 0, p0 = 0;
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    gk[k] = g.c[k] * (uint32_t)rs_ld<kRecLds>(rs.sf, j * D + k);
+    b = umod<kPow2>(b + al[k] * gk[k], L);
+    p0 = umod<kPow2>(p0 + ta[k] * gk[k], L);
+  }
+  a = rs_ld<kRecLds>(rs.sa, j);
+  bm = bmax[b];
+  bc = bcnt[b];
+  w[0] = tw[p0];
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    uint32_t p = p0 + gk[k];
+    if (p >= L) p -= L;
+    w[k + 1] = tw[p];
+  }
+  return b;
+}
+template <int D>
+__device__ __forceinline__ void entry_add(int2* Q, uint32_t L, uint32_t b, float2 a, uint32_t bm, int bc,
+                                          const float2 (&w)[D + 1]) {
+  const int e = bin_exponent32(bm, bc);
+#pragma unroll
+  for (int i = 0; i <= D; ++i) {
+    const float2 c = c_mulc(a, w[i]);
+    atomicAdd(&Q[i * L + b].x, fixed_term32(c.x, e));
+    atomicAdd(&Q[i * L + b].y, fixed_term32(c.y, e));
+  }
+}
+
 // Then every thread takes set entries j = j0, j0 + js, ... < n and adds
 // their projections on the D+1 lines to their bin's fixed-point sums in Q
 // (scale from the bin's largest amplitude and entry count; LDS integer
@@ -516,27 +557,11 @@ __device__ __forceinline__ void accumulate_bins(const Geo<D>& g, const uint32_t 
                                                 const int* bcnt, int2* Q, int j0, int js, int n) {
   const uint32_t L = g.L;
   for (int j = j0; j < n; j += js) {
-    uint32_t gk[D];
-    uint32_t b = 0, p0 = 0;
-#pragma unroll
-    for (int k = 0; k < D; ++k) {
-      gk[k] = g.c[k] * (uint32_t)rs_ld<kRecLds>(rs.sf, j * D + k);
-      b = umod<kPow2>(b + al[k] * gk[k], L);
-      p0 = umod<kPow2>(p0 + ta[k] * gk[k], L);
-    }
-    const float2 a = rs_ld<kRecLds>(rs.sa, j);
-    const int e = bin_exponent32(bmax[b], bcnt[b]);
-    float2 c = c_mulc(a, tw[p0]);
-    atomicAdd(&Q[b].x, fixed_term32(c.x, e));
-    atomicAdd(&Q[b].y, fixed_term32(c.y, e));
-#pragma unroll
-    for (int k = 0; k < D; ++k) {
-      uint32_t p = p0 + gk[k];
-      if (p >= L) p -= L;
-      c = c_mulc(a, tw[p]);
-      atomicAdd(&Q[(k + 1) * L + b].x, fixed_term32(c.x, e));
-      atomicAdd(&Q[(k + 1) * L + b].y, fixed_term32(c.y, e));
-    }
+    float2 a, w[D + 1];
+    uint32_t bm;
+    int bc;
+    const uint32_t b = entry_reads<D, kPow2, kRecLds>(g, al, ta, rs, tw, bmax, bcnt, j, a, bm, bc, w);
+    entry_add<D>(Q, L, b, a, bm, bc, w);
   }
 }
 
