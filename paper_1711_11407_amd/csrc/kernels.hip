@@ -1311,6 +1311,7 @@ __device__ __forceinline__ void backward_cube(const CubeDesc& cd, const OutPtrs 
   int* riter;       // [max_k] detection iterations (LDS, after abar)
   uint32_t* dgk;    // [max_k][D] c_k m_k of each detection's frequency
                     // (LDS); ~0 first: no valid set index
+  int* rbin;        // [max_k] detection bins (LDS)
   const float2* tw;
   if constexpr (kLinesWs) {
     rbar = (float2*)lines_ws;
@@ -1331,6 +1332,7 @@ __device__ __forceinline__ void backward_cube(const CubeDesc& cd, const OutPtrs 
   }
   riter = (int*)(abar + cd.max_k);
   dgk = (uint32_t*)(riter + cd.max_k);
+  rbin = (int*)(dgk + cd.max_k * D);
   __shared__ int sh_s, sh_t;
 
   // the set and the merged frequencies left out of it: every entry the
@@ -1343,6 +1345,7 @@ __device__ __forceinline__ void backward_cube(const CubeDesc& cd, const OutPtrs 
     const int si = ld_gi(fwd.rec_sin, i);
     abar[i] = (si >= 0 && si < nent) ? ld_g(ga, si) : make_float2(0.f, 0.f);
     riter[i] = ld_gi(fwd.rec_iter, i);
+    rbin[i] = ld_gi(fwd.rec_bin, i);
     const bool fok = si >= 0 && si < cd.max_k;
 #pragma unroll
     for (int q = 0; q < D; ++q)
@@ -1378,7 +1381,7 @@ __device__ __forceinline__ void backward_cube(const CubeDesc& cd, const OutPtrs 
     }
     // Detections of iteration t: distinct bins, so plain stores.
     for (int i = s0 + tid; i < e; i += B) {
-      const int m = ld_gi(fwd.rec_bin, i);
+      const int m = rbin[i];
       if (!t_ok || m < 0 || m >= (int)L || dgk[i * D] == ~0u) continue;
       uint32_t p = 0;
 #pragma unroll
