@@ -358,7 +358,8 @@ fpssft_status fpssft_lines_fft_all(fpssft_plan_t plan, const void* const* xs,
  * overwritten (zero off the sampled lines). UNSUPPORTED for
  * FPSSFT_FLAG_AMP_AVERAGE plans, and when a cube's LDS share exceeds
  * 160 KB: per detection its cotangent, iteration, frequency indices and
- * bin ((16 + 4 D) max_k bytes) plus,
+ * bin ((16 + 4 D) max_k bytes), 4 min(T, max_k) bytes of per-iteration
+ * indices, plus,
  * unless its lines live in the plan's device workspace (above), the line
  * cotangent and the FFT's second buffer (16 L bytes) and, for lines short
  * enough to be transformed with all D+1 in LDS, the twiddles (8 L

@@ -1296,6 +1296,82 @@ __global__ void k_zero(float2* const* __restrict__ bufs, const int64_t* __restri
 // kLinesWs (lines too long for LDS) the two line buffers are in the cube's
 // device workspace.
 // ---------------------------------------------------------------------------
+// The deferred iterations of the adjoint (64 <= L <= 512, a power of two):
+// up to two waves each take an iteration, spread its detections' values
+// over the line in their own LDS buffer, transform it in registers and add
+// the conjugate at the line-0 sample positions. A wave reads back only
+// what it wrote itself, in program order (no block barrier).
+template <int D, bool kPow2>
+__device__ __forceinline__ void backward_deferred(const CubeDesc& cd, const Geo<D>& g, const float2* abar,
+                                                  const int* riter, const int* rbin, const int* rstart, int nr,
+                                                  int n, const int32_t* __restrict__ sched, const float2* tw,
+                                                  float2* buf0, float2* buf1, float2* __restrict__ gx) {
+  const uint32_t L = g.L;
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  const int npw = min((int)(blockDim.x >> 6), 2);
+  if (wv >= npw) return;
+  const int E = (int)(L >> 6);
+  float2* buf = wv ? buf1 : buf0;
+  for (int r = wv; r < nr; r += npw) {
+    const int s0 = rstart[r];
+    const int e = r ? rstart[r - 1] : n;
+    const int t = riter[s0];
+    if (t < 0 || t >= cd.T) continue;
+    for (uint32_t m = lane; m < L; m += 64) buf[m] = make_float2(0.f, 0.f);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // the detections' bins are distinct within an iteration
+    for (int i = s0 + lane; i < e; i += 64) {
+      const int m = rbin[i];
+      if (m >= 0 && m < (int)L) buf[m] = c_scale(c_conj(abar[i]), cd.inv_L);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // the wave transform takes line element E q + e in register e of lane q
+    float2 v[kEMax];
+#pragma unroll
+    for (int q = 0; q < kEMax; ++q) v[q] = q < E ? buf[E * lane + q] : make_float2(0.f, 0.f);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    int32_t row[2 * D];
+#pragma unroll
+    for (int q = 0; q < 2 * D; ++q) row[q] = sched[cd.sched_off + t * 2 * D + q];
+    // s_bar(l) = conj(FFT(conj(r_bar) / L))(l), added at sample l of line 0
+    auto add = [&](int l, float2 val) {
+      int64_t step[D];
+      const int64_t flat = line_sample<D, kPow2>(g, row, (uint32_t)l, step);
+      unsafeAtomicAdd(&gx[flat].x, val.x);
+      unsafeAtomicAdd(&gx[flat].y, -val.y);
+    };
+    switch (E) {
+      case 1: {
+        float2 w[1] = {v[0]};
+        wave_fft_lanes<1>(w, tw, add);
+        break;
+      }
+      case 2: {
+        float2 w[2] = {v[0], v[1]};
+        wave_fft_lanes<2>(w, tw, add);
+        break;
+      }
+      case 4: {
+        float2 w[4] = {v[0], v[1], v[2], v[3]};
+        wave_fft_lanes<4>(w, tw, add);
+        break;
+      }
+      default: {
+        float2 w[8] = {v[0], v[1], v[2], v[3], v[4], v[5], v[6], v[7]};
+        wave_fft_lanes<8>(w, tw, add);
+        break;
+      }
+    }
+  }
+}
+
 template <int D, bool kPow2, bool kLinesWs>
 __device__ __forceinline__ void backward_cube(const CubeDesc& cd, const OutPtrs fwd, const float2* __restrict__ ga,
                                               float2* __restrict__ gx, const int32_t* __restrict__ sched,
@@ -1312,6 +1388,9 @@ __device__ __forceinline__ void backward_cube(const CubeDesc& cd, const OutPtrs 
   uint32_t* dgk;    // [max_k][D] c_k m_k of each detection's frequency
                     // (LDS); ~0 first: no valid set index
   int* rbin;        // [max_k] detection bins (LDS)
+  int* rstart;      // [min(T, max_k)] first detection of each iteration
+                    // whose line transform is deferred, last iteration
+                    // first (LDS)
   const float2* tw;
   if constexpr (kLinesWs) {
     rbar = (float2*)lines_ws;
@@ -1333,7 +1412,14 @@ __device__ __forceinline__ void backward_cube(const CubeDesc& cd, const OutPtrs 
   riter = (int*)(abar + cd.max_k);
   dgk = (uint32_t*)(riter + cd.max_k);
   rbin = (int*)(dgk + cd.max_k * D);
-  __shared__ int sh_s, sh_t;
+  rstart = rbin + cd.max_k;
+  const int rcap = min(cd.T, cd.max_k);
+  __shared__ int sh_s, sh_t, sh_nr, sh_def;
+  // Lines a wave can transform in registers (twiddles in LDS): the reverse
+  // recursion runs first, storing each detection's line-spectrum cotangent
+  // in its slot, and the iterations' inverse transforms and gradient adds
+  // follow, one iteration per wave, in parallel.
+  const bool par = kPow2 && !twg && L >= 64 && L <= 512 && B >= 64;
 
   // the set and the merged frequencies left out of it: every entry the
   // forward wrote is a sum of detections
@@ -1351,6 +1437,7 @@ __device__ __forceinline__ void backward_cube(const CubeDesc& cd, const OutPtrs 
     for (int q = 0; q < D; ++q)
       dgk[i * D + q] = fok ? g.c[q] * (uint32_t)ld_gi(fwd.freqs, si * D + q) : (q == 0 ? ~0u : 0u);
   }
+  if (tid == 0) sh_nr = 0;
   __syncthreads();
   int e = n;
   while (e > 0) {
@@ -1366,11 +1453,19 @@ __device__ __forceinline__ void backward_cube(const CubeDesc& cd, const OutPtrs 
       }
       sh_s = lo;
       sh_t = tt;
+      int d = 0;
+      if (par && sh_nr < rcap) {
+        rstart[sh_nr] = lo;
+        sh_nr = sh_nr + 1;
+        d = 1;
+      }
+      sh_def = d;
     }
     for (uint32_t m = tid; m < L; m += B) rbar[m] = make_float2(0.f, 0.f);
     __syncthreads();
     const int s0 = sh_s;
     const int t = sh_t;
+    const bool deferred = sh_def != 0;
     const bool t_ok = t >= 0 && t < cd.T;
     const int32_t* at = sched + cd.sched_off + (t_ok ? t : 0) * 2 * D;
     uint32_t al[D], ta[D];
@@ -1380,13 +1475,20 @@ __device__ __forceinline__ void backward_cube(const CubeDesc& cd, const OutPtrs 
       ta[q] = (uint32_t)at[D + q];
     }
     // Detections of iteration t: distinct bins, so plain stores.
+    // A deferred iteration keeps each detection's value in its own slot
+    // (zero for a skipped one), which nothing reads again in this loop.
     for (int i = s0 + tid; i < e; i += B) {
       const int m = rbin[i];
-      if (!t_ok || m < 0 || m >= (int)L || dgk[i * D] == ~0u) continue;
+      if (!t_ok || m < 0 || m >= (int)L || dgk[i * D] == ~0u) {
+        if (deferred) abar[i] = make_float2(0.f, 0.f);
+        continue;
+      }
       uint32_t p = 0;
 #pragma unroll
       for (int q = 0; q < D; ++q) p = umod<kPow2>(p + ta[q] * dgk[i * D + q], L);
-      rbar[m] = c_mulc(abar[i], tw[p]);
+      const float2 r = c_mulc(abar[i], tw[p]);
+      rbar[m] = r;
+      if (deferred) abar[i] = r;
     }
     __syncthreads();
     // Earlier detections that iteration t's construction-subtraction removed.
@@ -1403,6 +1505,10 @@ __device__ __forceinline__ void backward_cube(const CubeDesc& cd, const OutPtrs 
       abar[j] = c_sub(abar[j], c_mul(tw[p], v));
     }
     __syncthreads();
+    if (deferred) {
+      e = s0;
+      continue;
+    }
     // s_bar(l) = (1/L) sum_m r_bar(m) e^{+j 2 pi l m / L}
     //          = (1/L) conj(FFT(conj(r_bar)))(l).
     for (uint32_t m = tid; m < L; m += B) rbar[m] = c_scale(c_conj(rbar[m]), cd.inv_L);
@@ -1420,6 +1526,7 @@ __device__ __forceinline__ void backward_cube(const CubeDesc& cd, const OutPtrs 
     __syncthreads();
     e = s0;
   }
+  if (par) backward_deferred<D, kPow2>(cd, g, abar, riter, rbin, rstart, sh_nr, n, sched, tw, rbar, scratch, gx);
 }
 
 template <int D, bool kPow2, bool kLinesWs>

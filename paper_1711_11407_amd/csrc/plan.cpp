@@ -341,10 +341,12 @@ size_t lines_ws_bytes(const CubeDesc& c) {
 // LDS of the adjoint: the line cotangent and the FFT's second buffer (in the
 // line workspace when the lines are too long for LDS), the twiddles (read
 // from device memory for long lines), per detection its cotangent, its
-// iteration, c_k m_k of its frequency and its bin.
+// iteration, c_k m_k of its frequency and its bin, and per iteration (at
+// most max_k of them) the first detection of its run.
 size_t bwd_lds_bytes(const CubeDesc& c) {
   const size_t lines = c.serial == 2 ? 0 : (c.serial ? 2 : 3) * (size_t)c.L * sizeof(float2);
-  return lines + (size_t)c.max_k * (sizeof(float2) + (2 + (size_t)c.D) * sizeof(int)) + 64;
+  return lines + (size_t)c.max_k * (sizeof(float2) + (2 + (size_t)c.D) * sizeof(int)) +
+         (size_t)std::min(c.T, c.max_k) * sizeof(int) + 64;
 }
 
 // Line-FFT work-group LDS: two line buffers and the twiddle table.
