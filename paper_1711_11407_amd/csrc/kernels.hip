@@ -1296,6 +1296,27 @@ __global__ void k_zero(float2* const* __restrict__ bufs, const int64_t* __restri
 // kLinesWs (lines too long for LDS) the two line buffers are in the cube's
 // device workspace.
 // ---------------------------------------------------------------------------
+// First index of the run of equal iterations that ends at e - 1 (the
+// detection trace is in iteration order), found by one wave: each round
+// probes 64 evenly spaced indices of the remaining range at once. The
+// result is below e whatever the trace holds.
+__device__ __forceinline__ int run_first(const int* riter, int e) {
+  const int lane = threadIdx.x & 63;
+  const int tt = riter[e - 1];
+  int lo = 0, hi = e - 1;  // indices below lo hold earlier iterations
+  while (hi > lo) {
+    const int step = (hi - lo + 63) >> 6;
+    const int idx = lo + lane * step;
+    const bool below = idx <= hi && riter[idx] < tt;
+    const int cnt = __popcll(__ballot(below ? 1 : 0));
+    if (cnt == 0) break;
+    const int nlo = lo + (cnt - 1) * step + 1;
+    hi = min(lo + cnt * step, hi);
+    lo = nlo;
+  }
+  return min(lo, e - 1);
+}
+
 // The deferred iterations of the adjoint (64 <= L <= 512, a power of two):
 // up to two waves each take an iteration, spread its detections' values
 // over the line in their own LDS buffer, transform it in registers and add
@@ -1415,6 +1436,7 @@ __device__ __forceinline__ void backward_cube(const CubeDesc& cd, const OutPtrs 
   rstart = rbin + cd.max_k;
   const int rcap = min(cd.T, cd.max_k);
   __shared__ int sh_s, sh_t, sh_nr, sh_def;
+  __shared__ int32_t sh_row[2 * D];
   // Lines a wave can transform in registers (twiddles in LDS): the reverse
   // recursion runs first, storing each detection's line-spectrum cotangent
   // in its slot, and the iterations' inverse transforms and gradient adds
@@ -1437,43 +1459,53 @@ __device__ __forceinline__ void backward_cube(const CubeDesc& cd, const OutPtrs 
     for (int q = 0; q < D; ++q)
       dgk[i * D + q] = fok ? g.c[q] * (uint32_t)ld_gi(fwd.freqs, si * D + q) : (q == 0 ? ~0u : 0u);
   }
+  // The last wave finds each iteration's run and reads its schedule row
+  // while the others work on the iteration before; its lane 0 publishes
+  // them at the barrier that ends that iteration.
+  const int wl = (B >> 6) - 1;
+  const bool finder = (tid >> 6) == wl;
+  const bool pub = tid == (wl << 6);
+  int nx_s = 0, nx_t = 0;
+  int32_t nx_row[2 * D];
+  auto find_next = [&](int end) {
+    nx_s = run_first(riter, end);
+    nx_t = riter[nx_s];
+    const bool ok = nx_t >= 0 && nx_t < cd.T;
+#pragma unroll
+    for (int q = 0; q < 2 * D; ++q) nx_row[q] = ok ? sched[cd.sched_off + nx_t * 2 * D + q] : 0;
+  };
+  auto publish = [&]() {
+    sh_s = nx_s;
+    sh_t = nx_t;
+#pragma unroll
+    for (int q = 0; q < 2 * D; ++q) sh_row[q] = nx_row[q];
+    int d = 0;
+    if (par && sh_nr < rcap) {
+      rstart[sh_nr] = nx_s;
+      sh_nr = sh_nr + 1;
+      d = 1;
+    }
+    sh_def = d;
+  };
   if (tid == 0) sh_nr = 0;
+  __syncthreads();
+  if (finder && n > 0) find_next(n);
+  if (pub && n > 0) publish();
+  for (uint32_t m = tid; m < L; m += B) rbar[m] = make_float2(0.f, 0.f);
   __syncthreads();
   int e = n;
   while (e > 0) {
-    if (tid == 0) {
-      // the detections of iteration tt are the run ending at e - 1 (the
-      // trace is in iteration order): binary search for its first index
-      const int tt = riter[e - 1];
-      int lo = 0, hi = e - 1;  // riter[hi] == tt
-      while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (riter[mid] < tt) lo = mid + 1;
-        else hi = mid;
-      }
-      sh_s = lo;
-      sh_t = tt;
-      int d = 0;
-      if (par && sh_nr < rcap) {
-        rstart[sh_nr] = lo;
-        sh_nr = sh_nr + 1;
-        d = 1;
-      }
-      sh_def = d;
-    }
-    for (uint32_t m = tid; m < L; m += B) rbar[m] = make_float2(0.f, 0.f);
-    __syncthreads();
     const int s0 = sh_s;
     const int t = sh_t;
     const bool deferred = sh_def != 0;
     const bool t_ok = t >= 0 && t < cd.T;
-    const int32_t* at = sched + cd.sched_off + (t_ok ? t : 0) * 2 * D;
     uint32_t al[D], ta[D];
 #pragma unroll
     for (int q = 0; q < D; ++q) {
-      al[q] = (uint32_t)at[q];
-      ta[q] = (uint32_t)at[D + q];
+      al[q] = (uint32_t)sh_row[q];
+      ta[q] = (uint32_t)sh_row[D + q];
     }
+    const int32_t* at = sched + cd.sched_off + (t_ok ? t : 0) * 2 * D;
     // Detections of iteration t: distinct bins, so plain stores.
     // A deferred iteration keeps each detection's value in its own slot
     // (zero for a skipped one), which nothing reads again in this loop.
@@ -1490,6 +1522,7 @@ __device__ __forceinline__ void backward_cube(const CubeDesc& cd, const OutPtrs 
       rbar[m] = r;
       if (deferred) abar[i] = r;
     }
+    if (finder && s0 > 0) find_next(s0);
     __syncthreads();
     // Earlier detections that iteration t's construction-subtraction removed.
     for (int j = tid; j < s0; j += B) {
@@ -1505,24 +1538,26 @@ __device__ __forceinline__ void backward_cube(const CubeDesc& cd, const OutPtrs 
       abar[j] = c_sub(abar[j], c_mul(tw[p], v));
     }
     __syncthreads();
-    if (deferred) {
-      e = s0;
-      continue;
-    }
-    // s_bar(l) = (1/L) sum_m r_bar(m) e^{+j 2 pi l m / L}
-    //          = (1/L) conj(FFT(conj(r_bar)))(l).
-    for (uint32_t m = tid; m < L; m += B) rbar[m] = c_scale(c_conj(rbar[m]), cd.inv_L);
-    __syncthreads();
-    const float2* S = block_fft<kPow2>(rbar, scratch, 1, (int)L, cd.nstages, cd.radix, tw, kLinesWs);
-    if (t_ok) {
-      for (uint32_t l = tid; l < L; l += B) {
-        int64_t step[D];
-        const int64_t flat = line_sample<D, kPow2>(g, at, l, step);
-        const float2 v = c_conj(S[l]);
-        unsafeAtomicAdd(&gx[flat].x, v.x);
-        unsafeAtomicAdd(&gx[flat].y, v.y);
+    if (!deferred) {
+      // s_bar(l) = (1/L) sum_m r_bar(m) e^{+j 2 pi l m / L}
+      //          = (1/L) conj(FFT(conj(r_bar)))(l).
+      for (uint32_t m = tid; m < L; m += B) rbar[m] = c_scale(c_conj(rbar[m]), cd.inv_L);
+      __syncthreads();
+      const float2* S = block_fft<kPow2>(rbar, scratch, 1, (int)L, cd.nstages, cd.radix, tw, kLinesWs);
+      if (t_ok) {
+        for (uint32_t l = tid; l < L; l += B) {
+          int64_t step[D];
+          const int64_t flat = line_sample<D, kPow2>(g, at, l, step);
+          const float2 v = c_conj(S[l]);
+          unsafeAtomicAdd(&gx[flat].x, v.x);
+          unsafeAtomicAdd(&gx[flat].y, v.y);
+        }
       }
+      __syncthreads();
     }
+    // the next iteration
+    for (uint32_t m = tid; m < L; m += B) rbar[m] = make_float2(0.f, 0.f);
+    if (pub && s0 > 0) publish();
     __syncthreads();
     e = s0;
   }
