@@ -638,8 +638,14 @@ __device__ __forceinline__ bool decode_bin(const Geo<D>& g, const uint32_t (&al)
       const float u = ((float)g.dims[k] * phi) * kInv2Pi;
       const float v = rintf(u);
       if (gtol >= 0.f) cand = cand && (fabsf(u - v) <= gtol);
-      int fi = (int)v % (int)g.dims[k];
-      if (fi < 0) fi += (int)g.dims[k];
+      // [v]_{N_k}: a mask for power-of-two sides (two's complement)
+      int fi;
+      if constexpr (kPow2) {
+        fi = (int)v & ((int)g.dims[k] - 1);
+      } else {
+        fi = (int)v % (int)g.dims[k];
+        if (fi < 0) fi += (int)g.dims[k];
+      }
       f[k] = fi;
     }
   }
