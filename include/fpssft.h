@@ -322,7 +322,8 @@ fpssft_status fpssft_execute_noalloc(fpssft_plan_t plan, int32_t cube, const voi
 
 /* The same method (Sec. 2.2) for all cubes of the plan in one persistent
  * launch per kernel instantiation (each work-group solves the cube of its
- * index in an order of shortest lines first, then takes the next ones from
+ * index in an order of shortest lines first, smallest cubes first within a
+ * line length, then takes the next ones from
  * a device queue), replayed from a HIP graph or launched
  * directly (fpssft_tuning). xs: host array of `batch` device cube pointers;
  * outs: host array of `batch` output structs (device pointers inside).

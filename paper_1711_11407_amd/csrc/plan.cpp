@@ -216,7 +216,8 @@ fpssft_status hip_status(hipError_t e) {
 }  // namespace
 
 // Cubes served by one kernel instantiation: a contiguous slice of the
-// order array (shortest lines first) and of the line-FFT item list.
+// order array (shortest lines first, then smallest cubes) and of the
+// line-FFT item list.
 struct Group {
   fpssft::KernelKey key;
   int32_t L = 0;        // line length of its cubes (one-length groups), else 0
@@ -570,7 +571,10 @@ fpssft_status build_plan(const fpssft_desc* descs, int32_t batch, const fpssft_t
     if (p->group_of[a] != p->group_of[b]) return p->group_of[a] < p->group_of[b];
     const int64_t ca = (int64_t)(p->descs[a].D + 1) * p->descs[a].L;
     const int64_t cb = (int64_t)(p->descs[b].D + 1) * p->descs[b].L;
-    return ca < cb;
+    if (ca != cb) return ca < cb;
+    // for one line length, fewer samples means fewer distinct lines through
+    // the cube, so collisions recur and the chain of iterations runs longer
+    return p->descs[a].N < p->descs[b].N;
   });
   for (size_t gi = 0; gi < p->groups.size(); ++gi) {
     Group& g = p->groups[gi];
