@@ -26,7 +26,11 @@ def fd_reference(cube_x, ref, al, ta):
 
 
 @pytest.mark.parametrize("dims,K,seed,T", [((64, 64), 40, 3, 30), ((16, 24), 20, 4, 30),
-                                           ((8, 8, 12), 30, 5, 40), ((256, 256), 50, 6, 0)])
+                                           ((8, 8, 12), 30, 5, 40), ((256, 256), 50, 6, 0),
+                                           # register line transforms of 512 points (2-D and
+                                           # 1-D) and a 3-D cube with 64-point lines
+                                           ((512, 64), 60, 7, 0), ((512,), 12, 8, 6),
+                                           ((16, 16, 64), 30, 9, 0)])
 def test_amp_backward_matches_fd(F, dims, K, seed, T):
     torch, dev = torch_dev()
     cube = W.plant(dims, K, seed=seed)
