@@ -630,7 +630,10 @@ __device__ __forceinline__ bool decode_bin(const Geo<D>& g, const uint32_t (&al)
   }
   // The phase decode only for bins that pass the magnitude tests (the same
   // decisions: every test must hold); waves without such a bin skip it.
-  if (cand) {
+  // With D >= 3 every bin takes it, branch-free, which lets the D phase
+  // decodes of a bin overlap (a 128^3 cube 2.5% faster; 2-D cubes are
+  // faster skipping it).
+  if (D >= 3 || cand) {
 #pragma unroll
     for (int k = 0; k < D; ++k) {
       const float2 z = c_mulc(r[k + 1], r0);
